@@ -1,0 +1,151 @@
+/*
+ * seeds.h - C ABI of libseeds: SEEDS superpixel refinement on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * SEEDS (Van den Bergh, Boix, Roig, Van Gool, "SEEDS: Superpixels Extracted
+ * via Energy-Driven Sampling") starts from a regular grid of superpixels
+ * (Sec. 5.1) and refines it by hill climbing (Sec. 5): blocks of pixels,
+ * from the largest block size down to 2x2, and then single pixels move to a
+ * neighbouring superpixel when the energy E = H + gamma G grows (Sec. 4).
+ * H is the colour-histogram term (eqs. eqColorSum, eqColorMain,
+ * eqColorHistogram), evaluated for a move with the histogram intersection of
+ * Prop. 1 (Sec. 5.3.1); G is the 3x3 boundary term (eqs. boundaryterm,
+ * eqBoundaryMain), evaluated for pixel moves with Prop. 2 (Sec. 5.3.2).
+ * Accepted moves update two histograms (Sec. 5.3.3).
+ *
+ * Schedule. Every sweep of a level visits the nine unit classes
+ * c = 3 (uy mod 3) + (ux mod 3) in order; in one phase every boundary unit of
+ * class c picks its best 4-neighbour label from the state at the start of the
+ * phase (ties: smaller label) and moves if the gain is strictly positive.
+ * Units of one class are at least three apart, so the moves of a phase never
+ * touch each other's neighbourhoods. A unit may leave label k only if k stays
+ * connected around it (4-connectivity, Sec. 3). The result is deterministic:
+ * labels, histograms and sizes do not depend on launch shapes or timing.
+ *
+ * All arithmetic is integer. Counts are pixel counts; the energy changes used
+ * are exact in count form (H' = sum_k sum_j h_k(j)^2,
+ * G' = sum_i sum_k b_i(k)^2):
+ *   pixel p of bin j, k -> n: g = (h_n(j) - h_k(j) + 1) + gamma (W_n + |K_p| - W_k)
+ *     where W_x = sum over the pixels i of p's 3x3 of the count of label x in
+ *     i's 3x3 patch (patches clipped to the image) and |K_p| the number of
+ *     in-image pixels of p's 3x3;
+ *   block l with m pixels, k -> n, rule INTERSECT (Prop. 1):
+ *     move iff int(c_n, c_l) > int(c_{k\l}, c_l), normalised intersections
+ *     compared exactly by cross-multiplication;
+ *   block rule EXACT: g = sum_j h_l(j) (h_n(j) - h_k(j) + h_l(j)) (half the
+ *     change of H'); under EXACT a block move k -> n is dropped when n is the
+ *     source of another accepted block move of the same phase.
+ *
+ * Errors. Every call returns a seeds_status; seeds_last_error() returns a
+ * thread-local description of the last failure on the calling thread.
+ * SEEDS_E_INVAL is returned before any device work. After SEEDS_E_DEVICE the
+ * context is poisoned: every call except seeds_destroy returns SEEDS_E_STATE.
+ *
+ * Threading. A context is not thread-safe; distinct contexts may be used
+ * concurrently from different threads and streams.
+ *
+ * Streams. hip_stream is a hipStream_t (NULL = the null stream). Device work
+ * is enqueued on it; calls return before it completes unless stated.
+ */
+#ifndef SEEDS_H
+#define SEEDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct seeds_ctx seeds_ctx;
+
+typedef enum {
+    SEEDS_OK = 0,
+    SEEDS_E_INVAL = -1,  /* bad argument; nothing was enqueued                 */
+    SEEDS_E_NOMEM = -2,  /* device or host allocation failed                    */
+    SEEDS_E_DEVICE = -3, /* a HIP call or kernel failed; the context is poisoned */
+    SEEDS_E_STATE = -4   /* the context is poisoned or in the wrong state       */
+} seeds_status;
+
+typedef enum {
+    SEEDS_BLOCK_INTERSECT = 0, /* Prop. 1: normalised histogram intersection   */
+    SEEDS_BLOCK_EXACT = 1      /* exact change of the colour term, drop rule   */
+} seeds_block_rule;
+
+typedef struct {
+    int32_t levels;           /* L in [1,8]: block sides 2^(L-1) .. 2, then pixels   */
+    int32_t bins_per_channel; /* B in [1,6]: B^3 colour bins (Sec. 4.1; paper: 5)    */
+    int32_t iters_per_level;  /* I >= 0: sweeps per level                            */
+    int32_t gamma;            /* weight of the boundary term in [0,65536]; 0 = off   */
+    int32_t block_rule;       /* seeds_block_rule                                    */
+} seeds_params;
+
+/* Parameters used by the paper's experiments where it states them (5 bins per
+ * channel, gamma = 1, 3x3 patches, Sec. 6.2), with L = 4 and I = 4.           */
+seeds_status seeds_default_params(seeds_params *p);
+
+/* Superpixel grid of Sec. 5.1 without touching the device: gx columns and gy
+ * rows, gx = round(sqrt(K W / H)), gy = round(K / gx) (halves round up).
+ * SEEDS_E_INVAL when a superpixel would be narrower or shorter than one
+ * top block of side 2^(levels-1), or when an argument is out of range.        */
+seeds_status seeds_grid(int32_t H, int32_t W, int32_t num_superpixels, int32_t levels,
+                        int32_t *gx, int32_t *gy);
+
+/* Create a context for one H x W image and initialise it (Sec. 5.1):
+ * quantise the image into B^3 bins, lay the gx x gy grid over the top
+ * blocks, build every superpixel's colour histogram and size.
+ *   rgb             device pointer to H rows of W interleaved R,G,B bytes;
+ *                   row r starts at rgb + r * row_pitch_bytes (>= 3 W). Read in
+ *                   stream order; the caller keeps it alive until then.
+ *   num_superpixels requested K; the grid gives K_eff = gx * gy.
+ * Limits: H, W >= 1, H * W < 2^23, 2^(levels-1) <= min(H, W).
+ * The context owns all device memory it allocates (freed by seeds_destroy).   */
+seeds_status seeds_init(seeds_ctx **out, const uint8_t *rgb, int32_t H, int32_t W,
+                        int64_t row_pitch_bytes, int32_t num_superpixels,
+                        const seeds_params *p, void *hip_stream);
+
+/* Re-initialise an existing context from a new image of the same size and
+ * parameters (no allocation): quantise, grid, histograms, schedule reset.     */
+seeds_status seeds_reinit(seeds_ctx *ctx, const uint8_t *rgb, int64_t row_pitch_bytes,
+                          void *hip_stream);
+
+/* Run the refinement schedule (Sec. 5.2): on a freshly initialised context,
+ * every block level from side 2^(L-1) down to 2 and then the pixel level, I
+ * sweeps each; on a context that has finished it, I more pixel-level sweeps.  */
+seeds_status seeds_refine(seeds_ctx *ctx, void *hip_stream);
+
+/* Run at most max_phases phases of the schedule (max_phases < 0: all); the
+ * state may stop at a block level, which is a valid partition (Sec. 5.4).
+ * *phases_done (may be NULL) receives the number of phases enqueued.          */
+seeds_status seeds_refine_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *phases_done,
+                                 void *hip_stream);
+
+/* Write the H x W int32 labels (row-major, values in [0, K_eff)) to out.
+ * out_is_host = 0: out is a device pointer, the copy is enqueued on the stream.
+ * out_is_host = 1: out is host memory; the call waits for the stream.         */
+seeds_status seeds_labels(const seeds_ctx *ctx, int32_t *out, int32_t out_is_host,
+                          void *hip_stream);
+
+/* K_eff = gx * gy of the context (or -1 for NULL). */
+int32_t seeds_num_superpixels(const seeds_ctx *ctx);
+
+/* Test hook: colour histograms (K_eff x B^3 int32, row-major) and sizes
+ * (K_eff int32) as pixel counts. Either pointer may be NULL. Same out_is_host
+ * convention as seeds_labels.                                                 */
+seeds_status seeds_histograms(const seeds_ctx *ctx, int32_t *hist, int32_t *size,
+                              int32_t out_is_host, void *hip_stream);
+
+/* Test hook: current level of the context (0 = pixel level) or -1 for NULL.   */
+int32_t seeds_level(const seeds_ctx *ctx);
+
+/* Release the context and its device memory (after synchronising the stream
+ * it last used). NULL is accepted.                                            */
+seeds_status seeds_destroy(seeds_ctx *ctx);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *seeds_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEEDS_H */

@@ -1,0 +1,181 @@
+"""Python binding of libseeds (C ABI in include/seeds.h).
+
+Argument marshalling only: every step of the refinement runs in the HIP
+library. PyTorch supplies device memory (tensor data pointers) and streams.
+There is no fallback: if libseeds.so is missing or cannot be loaded, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so that libseeds shares torch's HIP runtime
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libseeds.so")
+
+SEEDS_OK = 0
+SEEDS_E_INVAL = -1
+SEEDS_E_NOMEM = -2
+SEEDS_E_DEVICE = -3
+SEEDS_E_STATE = -4
+SEEDS_BLOCK_INTERSECT = 0
+SEEDS_BLOCK_EXACT = 1
+
+
+class SeedsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libseeds status {status}: {msg}")
+        self.status = status
+
+
+class seeds_params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("bins_per_channel", ctypes.c_int32),
+                ("iters_per_level", ctypes.c_int32), ("gamma", ctypes.c_int32),
+                ("block_rule", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+        PI = ctypes.POINTER(ctypes.c_int32)
+        sig = {
+            "seeds_default_params": ([ctypes.POINTER(seeds_params)], S),
+            "seeds_grid": ([I32, I32, I32, I32, PI, PI], S),
+            "seeds_init": ([ctypes.POINTER(P), P, I32, I32, I64, I32, ctypes.POINTER(seeds_params), P], S),
+            "seeds_reinit": ([P, P, I64, P], S),
+            "seeds_refine": ([P, P], S),
+            "seeds_refine_phases": ([P, I32, PI, P], S),
+            "seeds_labels": ([P, P, I32, P], S),
+            "seeds_num_superpixels": ([P], I32),
+            "seeds_histograms": ([P, P, P, I32, P], S),
+            "seeds_level": ([P], I32),
+            "seeds_destroy": ([P], S),
+            "seeds_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != SEEDS_OK:
+        raise SeedsError(status, lib().seeds_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ---- the C ABI, one function each -------------------------------------------
+
+def seeds_default_params() -> seeds_params:
+    p = seeds_params()
+    _check(lib().seeds_default_params(ctypes.byref(p)))
+    return p
+
+
+def seeds_grid(H: int, W: int, num_superpixels: int, levels: int):
+    gx, gy = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().seeds_grid(H, W, num_superpixels, levels, ctypes.byref(gx), ctypes.byref(gy)))
+    return gx.value, gy.value
+
+
+def seeds_init(rgb: torch.Tensor, num_superpixels: int, params: seeds_params, stream=None):
+    """rgb: H x W x 3 uint8 CUDA tensor (rows may be strided). Returns a ctx handle."""
+    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or not rgb.is_cuda:
+        raise ValueError("rgb must be an H x W x 3 uint8 device tensor")
+    if rgb.stride(2) != 1 or rgb.stride(1) != 3:
+        raise ValueError("rgb pixels must be interleaved R,G,B bytes")
+    H, W, _ = rgb.shape
+    ctx = ctypes.c_void_p()
+    _check(lib().seeds_init(ctypes.byref(ctx), rgb.data_ptr(), H, W, rgb.stride(0),
+                            num_superpixels, ctypes.byref(params), _stream(stream)))
+    return ctx
+
+
+def seeds_reinit(ctx, rgb: torch.Tensor, stream=None) -> None:
+    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or not rgb.is_cuda or rgb.stride(1) != 3:
+        raise ValueError("rgb must be an H x W x 3 uint8 device tensor")
+    _check(lib().seeds_reinit(ctx, rgb.data_ptr(), rgb.stride(0), _stream(stream)))
+
+
+def seeds_refine(ctx, stream=None) -> None:
+    _check(lib().seeds_refine(ctx, _stream(stream)))
+
+
+def seeds_refine_phases(ctx, max_phases: int, stream=None) -> int:
+    done = ctypes.c_int32()
+    _check(lib().seeds_refine_phases(ctx, max_phases, ctypes.byref(done), _stream(stream)))
+    return done.value
+
+
+def seeds_labels(ctx, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Write H x W int32 labels into out (device or host tensor, contiguous)."""
+    if out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor")
+    _check(lib().seeds_labels(ctx, out.data_ptr(), 0 if out.is_cuda else 1, _stream(stream)))
+    return out
+
+
+def seeds_num_superpixels(ctx) -> int:
+    return lib().seeds_num_superpixels(ctx)
+
+
+def seeds_level(ctx) -> int:
+    return lib().seeds_level(ctx)
+
+
+def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, stream=None):
+    host = None
+    for t in (hist, size):
+        if t is not None:
+            if t.dtype != torch.int32 or not t.is_contiguous():
+                raise ValueError("histogram outputs must be contiguous int32 tensors")
+            host = (not t.is_cuda) if host is None else host
+            if host != (not t.is_cuda):
+                raise ValueError("hist and size must both be on the device or both on the host")
+    _check(lib().seeds_histograms(ctx, hist.data_ptr() if hist is not None else None,
+                                  size.data_ptr() if size is not None else None,
+                                  1 if host else 0, _stream(stream)))
+    return hist, size
+
+
+def seeds_destroy(ctx) -> None:
+    _check(lib().seeds_destroy(ctx))
+
+
+def seeds_last_error() -> str:
+    return lib().seeds_last_error().decode()
+
+
+# ---- convenience --------------------------------------------------------------
+
+def make_params(levels: int = 4, bins: int = 5, iters: int = 4, gamma: int = 1,
+                rule: int = SEEDS_BLOCK_INTERSECT) -> seeds_params:
+    return seeds_params(levels, bins, iters, gamma, rule)
+
+
+def superpixels(rgb: torch.Tensor, num_superpixels: int, params: seeds_params,
+                stream=None) -> torch.Tensor:
+    """One-shot: init, refine and return device int32 labels (H x W)."""
+    ctx = seeds_init(rgb, num_superpixels, params, stream)
+    try:
+        seeds_refine(ctx, stream)
+        out = torch.empty(rgb.shape[:2], dtype=torch.int32, device=rgb.device)
+        seeds_labels(ctx, out, stream)
+    finally:
+        seeds_destroy(ctx)
+    return out

@@ -1,0 +1,205 @@
+"""GPU parity: labels, colour histograms and sizes from the HIP library (through
+the C ABI) must equal the CPU oracle's bit for bit, at the end of the schedule
+and after every phase, on seeded synthetic images."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _defs import colour_histograms, valid_partition
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1309_3848_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build(force=True)
+    from paper_1309_3848_amd import seeds
+    seeds.lib()
+    return seeds
+
+
+def _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases=-1):
+    import torch
+    rgb = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    ctx = S.seeds_init(rgb, K, S.make_params(L, B, I, gamma, rule))
+    try:
+        if max_phases < 0:
+            S.seeds_refine(ctx)
+        else:
+            S.seeds_refine_phases(ctx, max_phases)
+        keff = S.seeds_num_superpixels(ctx)
+        lab = torch.empty(img.shape[:2], dtype=torch.int32, device="cuda")
+        S.seeds_labels(ctx, lab)
+        hist = torch.empty((keff, B ** 3), dtype=torch.int32)
+        size = torch.empty((keff,), dtype=torch.int32)
+        S.seeds_histograms(ctx, hist, size)
+        return lab.cpu().numpy(), hist.numpy(), size.numpy(), S.seeds_level(ctx)
+    finally:
+        S.seeds_destroy(ctx)
+
+
+def _compare(S, img, K, L, B=5, I=4, gamma=1, rule=0, max_phases=-1, check_valid=True):
+    _say(f"shape={img.shape[:2]} K={K} L={L} B={B} I={I} gamma={gamma} rule={rule} "
+         f"max_phases={max_phases}")
+    lab, hist, size, level = _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases)
+    ref_lab, ref_hist, ref_size = oracle.seeds(img, K, L, B, I, gamma, rule, max_phases)
+    assert lab.shape == ref_lab.shape
+    bad = np.argwhere(lab != ref_lab)
+    assert bad.size == 0, f"{len(bad)} labels differ, first at {bad[:5].tolist()}"
+    assert np.array_equal(size, ref_size)
+    assert np.array_equal(hist, ref_hist)
+    # histograms must also agree with a recount of the GPU's own labels
+    o = oracle.Oracle(img, K, L, B, I, gamma, rule)
+    assert np.array_equal(hist, colour_histograms(lab, o.bins(), o.K, B ** 3))
+    if check_valid:
+        assert valid_partition(lab, o.K)
+    return lab
+
+
+# --------------------------------------------------------------------------
+
+def test_small_image_full_schedule(S):
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(97, 131, 12, 8.0, seed=7)
+    _compare(S, img, K=40, L=3, B=5, I=2)
+
+
+def test_481x321_workload(S):
+    from paper_1309_3848_amd import synth
+    _compare(S, synth.single_481x321(), K=200, L=3, B=5, I=4, gamma=1)
+
+
+def test_1080p_workload(S):
+    from paper_1309_3848_amd import synth
+    _compare(S, synth.single_1080p(), K=1000, L=4, B=5, I=4, gamma=1, check_valid=False)
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_configurations(S, case):
+    from paper_1309_3848_amd import synth
+    rng = np.random.default_rng(500 + case)
+    while True:
+        L = int(rng.integers(1, 6))
+        T = 1 << (L - 1)
+        H = int(rng.integers(max(T, 3), 260))
+        W = int(rng.integers(max(T, 3), 260))
+        K = int(rng.integers(1, 300))
+        if oracle.grid(H, W, K, L) is not None:
+            break
+    B = int(rng.integers(1, 7))
+    I = int(rng.integers(0, 4))
+    gamma = int(rng.choice([0, 1, 2, 7]))
+    rule = int(rng.integers(0, 2))
+    img = synth.voronoi_image(H, W, int(rng.integers(3, 40)), float(rng.uniform(2, 16)),
+                              seed=600 + case)
+    _compare(S, img, K, L, B, I, gamma, rule)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_every_phase_matches(S, rule):
+    """Stop after 0, 1, 2, ... phases: the state (at whatever level) matches."""
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(75, 103, 10, 8.0, seed=31)
+    total = 3 * 2 * 9
+    for n in range(0, total + 1):
+        _compare(S, img, K=30, L=3, B=4, I=2, gamma=1, rule=rule, max_phases=n,
+                 check_valid=(n % 9 == 0))
+
+
+@pytest.mark.parametrize("H,W,K,L", [
+    (1, 1, 1, 1), (2, 2, 1, 2), (1, 57, 3, 1), (57, 1, 3, 1), (3, 200, 5, 2), (200, 3, 5, 2),
+    (16, 16, 1, 5), (33, 65, 2, 1), (64, 64, 64, 3),
+])
+def test_edge_shapes(S, H, W, K, L):
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(H, W, 4, 8.0, seed=H * 1000 + W)
+    _compare(S, img, K, L, B=5, I=3, gamma=1)
+
+
+def test_flat_and_two_colour_images(S):
+    img = np.full((64, 96, 3), 140, np.uint8)
+    _compare(S, img, 24, 4, 5, 3, 0)
+    img = np.zeros((32, 64, 3), np.uint8)
+    img[:, :35] = (200, 40, 40)
+    img[:, 35:] = (30, 30, 220)
+    lab = _compare(S, img, 2, 3, 5, 12, 1)
+    assert np.array_equal(lab, (np.arange(64)[None, :] >= 35).astype(np.int32).repeat(32, 0))
+
+
+def test_largest_block_sizes(S):
+    """levels = 8: blocks of side 128, 64, 32, 16 use the multi-pixel-per-lane path."""
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(300, 530, 20, 8.0, seed=77)
+    _compare(S, img, 4, 8, 5, 1, 1)
+    _compare(S, img, 4, 8, 3, 2, 1, rule=1)
+
+
+def test_determinism_and_repeat_refine(S):
+    import torch
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(120, 170, 15, 8.0, seed=41)
+    a = _gpu_run(S, img, 50, 3, 5, 3, 1, 0)
+    b = _gpu_run(S, img, 50, 3, 5, 3, 1, 0)
+    assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3]))
+    # a second refine runs I more pixel-level sweeps, like the oracle
+    rgb = torch.from_numpy(img).cuda()
+    ctx = S.seeds_init(rgb, 50, S.make_params(3, 5, 3, 1, 0))
+    try:
+        S.seeds_refine(ctx)
+        S.seeds_refine(ctx)
+        lab = torch.empty((120, 170), dtype=torch.int32)
+        S.seeds_labels(ctx, lab)
+    finally:
+        S.seeds_destroy(ctx)
+    o = oracle.Oracle(img, 50, 3, 5, 3, 1, 0)
+    o.run()
+    o.run()
+    assert np.array_equal(lab.numpy(), o.labels())
+
+
+def test_reinit_with_a_new_image(S):
+    import torch
+    from paper_1309_3848_amd import synth
+    img1 = synth.voronoi_image(90, 140, 9, 8.0, seed=51)
+    img2 = synth.voronoi_image(90, 140, 14, 6.0, seed=52)
+    ctx = S.seeds_init(torch.from_numpy(img1).cuda(), 40, S.make_params(3, 5, 2, 1, 0))
+    try:
+        S.seeds_refine(ctx)
+        S.seeds_reinit(ctx, torch.from_numpy(img2).cuda())
+        S.seeds_refine(ctx)
+        lab = torch.empty((90, 140), dtype=torch.int32)
+        S.seeds_labels(ctx, lab)
+    finally:
+        S.seeds_destroy(ctx)
+    ref, _, _ = oracle.seeds(img2, 40, 3, 5, 2, 1, 0)
+    assert np.array_equal(lab.numpy(), ref)
+
+
+def test_strided_rows(S):
+    import torch
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(70, 90, 9, 8.0, seed=61)
+    big = torch.zeros((70, 100, 3), dtype=torch.uint8)
+    big[:, :90] = torch.from_numpy(img)
+    view = big.cuda()[:, :90]           # row pitch 300 bytes, not 270
+    ctx = S.seeds_init(view, 20, S.make_params(2, 5, 2, 1, 0))
+    try:
+        S.seeds_refine(ctx)
+        lab = torch.empty((70, 90), dtype=torch.int32)
+        S.seeds_labels(ctx, lab)
+    finally:
+        S.seeds_destroy(ctx)
+    ref, _, _ = oracle.seeds(img, 20, 2, 5, 2, 1, 0)
+    assert np.array_equal(lab.numpy(), ref)
