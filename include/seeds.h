@@ -137,6 +137,26 @@ seeds_status seeds_histograms(const seeds_ctx *ctx, int32_t *hist, int32_t *size
 /* Test hook: current level of the context (0 = pixel level) or -1 for NULL.   */
 int32_t seeds_level(const seeds_ctx *ctx);
 
+typedef enum {
+    SEEDS_LAUNCH_GRAPH = 0,      /* default: one kernel per phase, the launches of a
+                                    whole refine call captured once into a HIP
+                                    graph and replayed (partial runs launch
+                                    directly)                                     */
+    SEEDS_LAUNCH_STEPS = 1,      /* the same kernels, launched one by one         */
+    SEEDS_LAUNCH_PERSISTENT = 2  /* one cooperative launch per refine call with
+                                    grid-wide barriers between phases             */
+} seeds_launch_mode;
+
+/* Choose how later refine calls are launched. Results are identical in both
+ * modes; the mode only changes the launch structure.                         */
+seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
+
+/* Wait for the stream and report device-side failures of earlier refine
+ * calls (a grid barrier that timed out, an overflowing move log) as
+ * SEEDS_E_DEVICE. seeds_labels and seeds_histograms with host outputs do the
+ * same check.                                                                */
+seeds_status seeds_sync(seeds_ctx *ctx, void *hip_stream);
+
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */
 seeds_status seeds_destroy(seeds_ctx *ctx);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "seeds.h"
@@ -28,17 +29,34 @@ seeds_status fail(seeds_status st, const char *fmt, ...) {
 
 }  // namespace
 
+// A refinement captured as a HIP graph, replayed while the schedule starts
+// from the same cursor.
+struct CachedGraph {
+    bool valid = false;
+    Sched start{}, end{};
+    int start_bl = 0, end_bl = 0;
+    int32_t phases = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+constexpr int kGraphSlots = 4;
+
 struct seeds_ctx {
     Dims d;
     int device;
     void *slab;  // one device allocation holding every buffer
     Buffers b;
-    // state of the partition: the unit grid of `level` holds the labels
-    // (bl[cur_bl] for block levels, b.lab for pixels)
-    int level;
+    PersistentGeom geom;
+    int log_groups, log_cap;  // move-log shape of the per-phase launches
+    int mode;    // seeds_launch_mode
+    hipStream_t capture;      // private stream used only to capture graphs
+    CachedGraph graphs[kGraphSlots];
+    int next_slot;
+    // state of the partition: the unit grid of sched.level holds the labels
+    // (bl[cur_bl] for block levels, b.lab for pixels); sched also holds the
+    // next phase of the schedule
+    Sched sched;
     int cur_bl;
-    // schedule cursor: the next phase is (cur_level, cur_sweep, cur_class)
-    int cur_level, cur_sweep, cur_class;
     bool cold;      // the first, hierarchical schedule is still running
     bool poisoned;  // a device error happened: only destroy is allowed
     uint32_t stamp; // phase counter, stamps move sources for the drop rule
@@ -109,12 +127,13 @@ seeds_status check_params(int32_t H, int32_t W, int32_t K, const seeds_params *p
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Layout of the context's single device allocation.
+// Layout of the context's single device allocation. The two histogram
+// copies are contiguous, and so are the two size copies.
 struct Layout {
-    size_t bins, lab, bl0, bl1, hist, size, src, pend, total;
+    size_t bins, lab, bl0, bl1, hist, size, src, pend, log, log_n, sync, total;
 };
 
-Layout layout_of(const Dims &d) {
+Layout layout_of(const Dims &d, const PersistentGeom &g, int phase_groups_, int phase_cap) {
     const size_t N = (size_t)d.H * d.W;
     const size_t blk = d.L > 1 ? (size_t)units_w(d, 1) * units_h(d, 1) : 0;
     const size_t pend = (size_t)class_cols(d.W, 0) * class_rows(d.H, 0);  // largest class
@@ -124,92 +143,197 @@ Layout layout_of(const Dims &d) {
     l.lab = off;  off += align_up(N * 4);
     l.bl0 = off;  off += align_up(blk * 4);
     l.bl1 = off;  off += align_up(blk * 4);
-    l.hist = off; off += align_up((size_t)d.K * d.hs * 4);
-    l.size = off; off += align_up((size_t)d.K * 4);
+    l.hist = off; off += align_up(2 * (size_t)d.K * d.hs * 4);
+    l.size = off; off += align_up(2 * (size_t)d.K * 4);
     l.src = off;  off += align_up((size_t)d.K * 4);
     l.pend = off; off += align_up(pend * 4);
+    const size_t entries = std::max((size_t)g.groups * g.log_cap, (size_t)phase_groups_ * phase_cap);
+    l.log = off;  off += align_up(2 * entries * 16);
+    l.log_n = off; off += align_up(2 * (size_t)std::max(g.groups, phase_groups_) * 4);
+    l.sync = off; off += align_up(4 * 4);
     l.total = off;
     return l;
 }
 
 int32_t *current_units(seeds_ctx *ctx) {
-    return ctx->level == 0 ? ctx->b.lab : ctx->b.bl[ctx->cur_bl];
+    return ctx->sched.level == 0 ? ctx->b.lab : ctx->b.bl[ctx->cur_bl];
 }
 
 seeds_status start_schedule(seeds_ctx *ctx, const uint8_t *rgb, int64_t pitch, hipStream_t s) {
     const Dims &d = ctx->d;
-    ctx->level = d.L - 1;
     ctx->cur_bl = 0;
     int32_t *top = d.L > 1 ? ctx->b.bl[0] : ctx->b.lab;
     hipError_t e = launch_init(d, ctx->b, rgb, pitch, top, s);
-    if (e == hipSuccess) e = launch_fill(ctx->b.src, 0, d.K, s);
     if (e != hipSuccess) return device_error(ctx, e, "init launch");
-    ctx->cur_level = d.L - 1;
-    ctx->cur_sweep = 0;
-    ctx->cur_class = 0;
+    ctx->sched.level = d.L - 1;
+    ctx->sched.cur_level = d.L - 1;
+    ctx->sched.cur_sweep = 0;
+    ctx->sched.cur_class = 0;
     ctx->cold = true;
     ctx->last_stream = s;
     return SEEDS_OK;
 }
 
-// Split the current level's blocks into their 2x2 children.
-seeds_status descend(seeds_ctx *ctx, hipStream_t s) {
+// Split the current level's blocks into their 2x2 children (per-step path).
+hipError_t descend_steps(seeds_ctx *ctx, hipStream_t s) {
     const Dims &d = ctx->d;
-    const int from = ctx->level;
-    hipError_t e;
-    if (from == 1) {
-        e = launch_expand(d, ctx->b.bl[ctx->cur_bl], 1, ctx->b.lab, s);
-    } else {
-        e = launch_upsample(ctx->b.bl[ctx->cur_bl], units_w(d, from), units_h(d, from),
-                            ctx->b.bl[1 - ctx->cur_bl], units_w(d, from - 1),
-                            units_h(d, from - 1), s);
-        ctx->cur_bl = 1 - ctx->cur_bl;
+    const int from = ctx->sched.level;
+    if (from == 1) return launch_expand(d, ctx->b.bl[ctx->cur_bl], 1, ctx->b.lab, s);
+    hipError_t e = launch_upsample(ctx->b.bl[ctx->cur_bl], units_w(d, from), units_h(d, from),
+                                   ctx->b.bl[1 - ctx->cur_bl], units_w(d, from - 1),
+                                   units_h(d, from - 1), s);
+    ctx->cur_bl = 1 - ctx->cur_bl;
+    return e;
+}
+
+// Enqueue the schedule from the current cursor as per-phase launches (at
+// most max_phases phases; < 0: all), ending with the replay that makes both
+// histogram copies equal again.
+seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out, hipStream_t s) {
+    const Dims &d = ctx->d;
+    const bool exact = d.rule == SEEDS_BLOCK_EXACT;
+    int32_t done = 0;
+    int par = 0, prev_groups = 0;
+    uint32_t stamp = 0;
+    hipError_t e = hipSuccess;
+    if (exact) e = launch_fill(ctx->b.src, 0, d.K, s);
+    for (;;) {
+        if (e != hipSuccess) return device_error(ctx, e, "phase launch");
+        int cls;
+        const SchedOp op = sched_next(d, ctx->sched, max_phases < 0 ? -1 : max_phases - done, &cls);
+        if (op == OP_END) break;
+        if (op == OP_DESCEND) {
+            e = descend_steps(ctx, s);
+        } else {
+            const int level = ctx->sched.level;
+            ++stamp;
+            if (level > 0 && exact) {
+                e = launch_phase_kernel(d, ctx->b, ctx->log_groups, ctx->log_cap, level, cls, par,
+                                        1, stamp, ctx->cur_bl, prev_groups, s);
+                if (e == hipSuccess)
+                    e = launch_phase_kernel(d, ctx->b, ctx->log_groups, ctx->log_cap, level, cls,
+                                            par, 2, stamp, ctx->cur_bl, 0, s);
+            } else {
+                e = launch_phase_kernel(d, ctx->b, ctx->log_groups, ctx->log_cap, level, cls, par,
+                                        0, stamp, ctx->cur_bl, prev_groups, s);
+            }
+            prev_groups = phase_groups(d, level, cls);
+            par ^= 1;
+            ++done;
+        }
+        sched_done(ctx->sched, op);
     }
-    if (e != hipSuccess) return device_error(ctx, e, "level transition launch");
-    ctx->level = from - 1;
+    if (done > 0)
+        e = launch_phase_kernel(d, ctx->b, ctx->log_groups, ctx->log_cap, -1, 0, par ^ 1, 0, 0, 0,
+                                prev_groups, s);
+    if (e != hipSuccess) return device_error(ctx, e, "replay launch");
+    if (done_out) *done_out = done;
+    return SEEDS_OK;
+}
+
+bool same_sched(const Sched &a, const Sched &b) {
+    return a.level == b.level && a.cur_level == b.cur_level && a.cur_sweep == b.cur_sweep &&
+           a.cur_class == b.cur_class;
+}
+
+// Full refinement from the current cursor through a cached graph (captured
+// on the first call from this cursor).
+seeds_status run_graph(seeds_ctx *ctx, int32_t *done_out, hipStream_t s) {
+    for (auto &g : ctx->graphs)
+        if (g.valid && same_sched(g.start, ctx->sched) && g.start_bl == ctx->cur_bl) {
+            hipError_t e = hipGraphLaunch(g.exec, s);
+            if (e != hipSuccess) return device_error(ctx, e, "hipGraphLaunch");
+            ctx->sched = g.end;
+            ctx->cur_bl = g.end_bl;
+            if (done_out) *done_out = g.phases;
+            return SEEDS_OK;
+        }
+    CachedGraph &g = ctx->graphs[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kGraphSlots;
+    if (g.valid) {
+        (void)hipGraphExecDestroy(g.exec);
+        g.valid = false;
+    }
+    g.start = ctx->sched;
+    g.start_bl = ctx->cur_bl;
+    hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return device_error(ctx, e, "hipStreamBeginCapture");
+    int32_t done = 0;
+    seeds_status st = enqueue_phases(ctx, -1, &done, ctx->capture);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture, &graph);
+    if (st != SEEDS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return device_error(ctx, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return device_error(ctx, e, "hipGraphInstantiate");
+    g.end = ctx->sched;
+    g.end_bl = ctx->cur_bl;
+    g.phases = done;
+    g.valid = true;
+    e = hipGraphLaunch(g.exec, s);
+    if (e != hipSuccess) return device_error(ctx, e, "hipGraphLaunch");
+    if (done_out) *done_out = done;
     return SEEDS_OK;
 }
 
 seeds_status run_schedule(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out, hipStream_t s) {
     const Dims &d = ctx->d;
+    if (!ctx->cold && ctx->sched.cur_level < 0) {  // finished: another I pixel sweeps
+        ctx->sched.cur_level = 0;
+        ctx->sched.cur_sweep = 0;
+        ctx->sched.cur_class = 0;
+    }
     int32_t done = 0;
-    if (!ctx->cold && ctx->cur_level < 0) {  // finished: another I pixel sweeps
-        ctx->cur_level = 0;
-        ctx->cur_sweep = 0;
-        ctx->cur_class = 0;
+    seeds_status st = SEEDS_OK;
+    if (ctx->mode == SEEDS_LAUNCH_PERSISTENT) {
+        // one launch; the host walks the same schedule to keep its cursor
+        const Sched start = ctx->sched;
+        const int start_bl = ctx->cur_bl;
+        int ops = 0;
+        for (;;) {
+            int cls;
+            const SchedOp op = sched_next(d, ctx->sched, max_phases < 0 ? -1 : max_phases - done, &cls);
+            if (op == OP_END) break;
+            if (op == OP_DESCEND && ctx->sched.level > 1) ctx->cur_bl ^= 1;
+            if (op == OP_PHASE) ++done;
+            sched_done(ctx->sched, op);
+            ++ops;
+        }
+        if (ops) {
+            hipError_t e = hipSuccess;
+            if (d.rule == SEEDS_BLOCK_EXACT) e = launch_fill(ctx->b.src, 0, d.K, s);
+            if (e == hipSuccess)
+                e = launch_refine(d, ctx->b, ctx->geom, start, start_bl, max_phases, 0, s);
+            if (e != hipSuccess) return device_error(ctx, e, "persistent refine launch");
+        }
+    } else if (ctx->mode == SEEDS_LAUNCH_GRAPH && max_phases < 0) {
+        st = run_graph(ctx, &done, s);
+    } else {
+        st = enqueue_phases(ctx, max_phases, &done, s);
     }
-    while (ctx->cur_level >= 0) {
-        if (ctx->cur_sweep >= d.I) {
-            --ctx->cur_level;
-            ctx->cur_sweep = 0;
-            ctx->cur_class = 0;
-            continue;
-        }
-        if (max_phases >= 0 && done >= max_phases) break;
-        while (ctx->level > ctx->cur_level) {
-            seeds_status st = descend(ctx, s);
-            if (st != SEEDS_OK) return st;
-        }
-        int32_t *units = current_units(ctx);
-        ++ctx->stamp;
-        hipError_t e = launch_phase(d, ctx->b, ctx->level, units, units, ctx->cur_class,
-                                    ctx->stamp, s);
-        if (e != hipSuccess) return device_error(ctx, e, "phase launch");
-        ++done;
-        if (++ctx->cur_class == 9) {
-            ctx->cur_class = 0;
-            ++ctx->cur_sweep;
-        }
-    }
-    if (ctx->cur_level < 0) {
-        while (ctx->level > 0) {
-            seeds_status st = descend(ctx, s);
-            if (st != SEEDS_OK) return st;
-        }
-        ctx->cold = false;
-    }
+    if (st != SEEDS_OK) return st;
+    if (ctx->sched.cur_level < 0) ctx->cold = false;
     ctx->last_stream = s;
     if (done_out) *done_out = done;
+    return SEEDS_OK;
+}
+
+// Device-side failure flag of the persistent kernel (barrier time-out or a
+// full move log); read after the stream has drained.
+seeds_status check_device_flag(seeds_ctx *ctx, hipStream_t s) {
+    uint32_t flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, ctx->b.sync + 2, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(ctx, e, "synchronise");
+    if (flag) {
+        ctx->poisoned = true;
+        return fail(SEEDS_E_DEVICE, flag == 2 ? "persistent kernel: move log overflow"
+                                              : "persistent kernel: grid barrier timed out");
+    }
     return SEEDS_OK;
 }
 
@@ -260,9 +384,19 @@ seeds_status seeds_init(seeds_ctx **out, const uint8_t *rgb, int32_t H, int32_t 
         delete ctx;
         return fail(SEEDS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     }
-    const Layout l = layout_of(d);
+    ctx->geom = persistent_geometry(d, ctx->device, 2);
+    phase_log_shape(d, &ctx->log_groups, &ctx->log_cap);
+    ctx->mode = SEEDS_LAUNCH_GRAPH;
+    ctx->next_slot = 0;
+    e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(SEEDS_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    const Layout l = layout_of(d, ctx->geom, ctx->log_groups, ctx->log_cap);
     e = hipMalloc(&ctx->slab, l.total);
     if (e != hipSuccess) {
+        (void)hipStreamDestroy(ctx->capture);
         delete ctx;
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? SEEDS_E_NOMEM : SEEDS_E_DEVICE,
@@ -273,14 +407,29 @@ seeds_status seeds_init(seeds_ctx **out, const uint8_t *rgb, int32_t H, int32_t 
     ctx->b.lab = (int32_t *)(base + l.lab);
     ctx->b.bl[0] = (int32_t *)(base + l.bl0);
     ctx->b.bl[1] = (int32_t *)(base + l.bl1);
-    ctx->b.hist = (int32_t *)(base + l.hist);
-    ctx->b.size = (int32_t *)(base + l.size);
+    ctx->b.hist[0] = (int32_t *)(base + l.hist);
+    ctx->b.hist[1] = ctx->b.hist[0] + (size_t)d.K * d.hs;
+    ctx->b.size[0] = (int32_t *)(base + l.size);
+    ctx->b.size[1] = ctx->b.size[0] + d.K;
     ctx->b.src = (int32_t *)(base + l.src);
     ctx->b.pend = (int32_t *)(base + l.pend);
+    ctx->b.log = (int4 *)(base + l.log);
+    ctx->b.log_n = (int32_t *)(base + l.log_n);
+    ctx->b.sync = (uint32_t *)(base + l.sync);
     ctx->stamp = 0;
+    e = launch_fill(ctx->b.src, 0, d.K, (hipStream_t)hip_stream);
+    if (e == hipSuccess) e = launch_fill((int32_t *)ctx->b.sync, 0, 4, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->slab);
+        (void)hipStreamDestroy(ctx->capture);
+        delete ctx;
+        return fail(SEEDS_E_DEVICE, "init fill: %s", hipGetErrorString(e));
+    }
     st = start_schedule(ctx, rgb, row_pitch_bytes, (hipStream_t)hip_stream);
     if (st != SEEDS_OK) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
         (void)hipFree(ctx->slab);
+        (void)hipStreamDestroy(ctx->capture);
         delete ctx;
         return st;
     }
@@ -327,10 +476,10 @@ seeds_status seeds_labels(const seeds_ctx *cctx, int32_t *out, int32_t out_is_ho
         if (e != hipSuccess) return device_error(nullptr, e, "hipMallocAsync");
         dst = (int32_t *)stage;
     }
-    if (ctx->level == 0)
+    if (ctx->sched.level == 0)
         e = hipMemcpyAsync(dst, ctx->b.lab, bytes, hipMemcpyDeviceToDevice, s);
     else
-        e = launch_expand(d, ctx->b.bl[ctx->cur_bl], ctx->level, dst, s);
+        e = launch_expand(d, ctx->b.bl[ctx->cur_bl], ctx->sched.level, dst, s);
     if (e == hipSuccess && out_is_host) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s);
     if (out_is_host) {
         hipError_t e2 = hipFreeAsync(stage, s);
@@ -338,12 +487,27 @@ seeds_status seeds_labels(const seeds_ctx *cctx, int32_t *out, int32_t out_is_ho
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) return device_error(ctx, e, "labels copy");
+    if (out_is_host) return check_device_flag(ctx, s);
     return SEEDS_OK;
 }
 
 int32_t seeds_num_superpixels(const seeds_ctx *ctx) { return ctx ? ctx->d.K : -1; }
 
-int32_t seeds_level(const seeds_ctx *ctx) { return ctx ? ctx->level : -1; }
+int32_t seeds_level(const seeds_ctx *ctx) { return ctx ? ctx->sched.level : -1; }
+
+seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode) {
+    if (!ctx) return fail(SEEDS_E_INVAL, "ctx is NULL");
+    if (mode != SEEDS_LAUNCH_GRAPH && mode != SEEDS_LAUNCH_PERSISTENT && mode != SEEDS_LAUNCH_STEPS)
+        return fail(SEEDS_E_INVAL, "unknown launch mode %d", mode);
+    ctx->mode = mode;
+    return SEEDS_OK;
+}
+
+seeds_status seeds_sync(seeds_ctx *ctx, void *hip_stream) {
+    if (!ctx) return fail(SEEDS_E_INVAL, "ctx is NULL");
+    if (ctx->poisoned) return fail(SEEDS_E_STATE, "context is poisoned by an earlier device error");
+    return check_device_flag(ctx, (hipStream_t)hip_stream);
+}
 
 seeds_status seeds_histograms(const seeds_ctx *cctx, int32_t *hist, int32_t *size,
                               int32_t out_is_host, void *hip_stream) {
@@ -355,19 +519,24 @@ seeds_status seeds_histograms(const seeds_ctx *cctx, int32_t *hist, int32_t *siz
     const hipMemcpyKind kind = out_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     hipError_t e = hipSuccess;
     if (hist)
-        e = hipMemcpy2DAsync(hist, (size_t)d.nb * 4, ctx->b.hist, (size_t)d.hs * 4,
+        e = hipMemcpy2DAsync(hist, (size_t)d.nb * 4, ctx->b.hist[0], (size_t)d.hs * 4,
                              (size_t)d.nb * 4, d.K, kind, s);
     if (e == hipSuccess && size)
-        e = hipMemcpyAsync(size, ctx->b.size, (size_t)d.K * 4, kind, s);
+        e = hipMemcpyAsync(size, ctx->b.size[0], (size_t)d.K * 4, kind, s);
     if (e == hipSuccess && out_is_host) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_error(ctx, e, "histogram copy");
+    if (out_is_host) return check_device_flag(ctx, s);
     return SEEDS_OK;
 }
 
 seeds_status seeds_destroy(seeds_ctx *ctx) {
     if (!ctx) return SEEDS_OK;
+    // the stream must drain before the memory goes (also after a device error)
     hipError_t e = hipStreamSynchronize(ctx->last_stream);
+    for (auto &g : ctx->graphs)
+        if (g.valid) (void)hipGraphExecDestroy(g.exec);
     hipError_t e2 = hipFree(ctx->slab);
+    (void)hipStreamDestroy(ctx->capture);
     delete ctx;
     if (e != hipSuccess) return fail(SEEDS_E_DEVICE, "destroy: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(SEEDS_E_DEVICE, "hipFree: %s", hipGetErrorString(e2));

@@ -1,0 +1,161 @@
+// Device helpers shared by the per-step kernels and the persistent kernel.
+#pragma once
+
+#include "seeds_internal.h"
+
+namespace seeds {
+
+// Neighbourhood of a unit on a unit grid: the ring mask (bit i: ring cell i
+// of N, NE, E, SE, S, SW, W, NW carries label k), the distinct labels other
+// than k among the four edge neighbours in ascending order (unused slots
+// hold kNoLabel, which sorts last), and whether k stays connected without the
+// unit.
+constexpr int kNoLabel = 0x7FFFFFFF;
+
+struct Neighbourhood {
+    int k;
+    int nc;
+    int cand[4];
+    bool movable;  // boundary unit whose removal keeps k connected
+};
+
+// k stays 4-connected around the unit iff the edge neighbours of label k lie
+// in one cyclic run of k cells on the ring (consecutive ring cells are
+// 4-adjacent); a run made of a lone corner touches no edge neighbour and does
+// not count. With no edge neighbour of label k the unit is all of k.
+__device__ __forceinline__ bool ring_keeps_connected(uint32_t r) {
+    if (!(r & 0x55u)) return false;
+    if (r == 0xFFu) return true;
+    const uint32_t prev = ((r << 1) | (r >> 7)) & 0xFFu;  // bit i: cell i-1
+    const uint32_t next = ((r >> 1) | (r << 7)) & 0xFFu;  // bit i: cell i+1
+    const uint32_t starts = r & ~prev;
+    const uint32_t lone_corners = r & ~prev & ~next & 0xAAu;
+    return __popc(starts) - __popc(lone_corners) == 1;
+}
+
+__device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict__ units, int uw,
+                                                       int uh, int ux, int uy) {
+    Neighbourhood nb;
+    const int64_t row = (int64_t)uy * uw;
+    nb.k = units[row + ux];
+    const bool hasN = uy > 0, hasS = uy + 1 < uh, hasW = ux > 0, hasE = ux + 1 < uw;
+    const int lN = hasN ? units[row - uw + ux] : -1;
+    const int lS = hasS ? units[row + uw + ux] : -1;
+    const int lW = hasW ? units[row + ux - 1] : -1;
+    const int lE = hasE ? units[row + ux + 1] : -1;
+    const int lNE = hasN && hasE ? units[row - uw + ux + 1] : -1;
+    const int lSE = hasS && hasE ? units[row + uw + ux + 1] : -1;
+    const int lSW = hasS && hasW ? units[row + uw + ux - 1] : -1;
+    const int lNW = hasN && hasW ? units[row - uw + ux - 1] : -1;
+    const int k = nb.k;
+    const uint32_t r = (lN == k) | (lNE == k) << 1 | (lE == k) << 2 | (lSE == k) << 3 |
+                       (lS == k) << 4 | (lSW == k) << 5 | (lW == k) << 6 | (lNW == k) << 7;
+    // edge neighbours, keeping the first occurrence of each other label
+    int c0 = (lN < 0 || lN == k) ? kNoLabel : lN;
+    int c1 = (lE < 0 || lE == k || lE == c0) ? kNoLabel : lE;
+    int c2 = (lS < 0 || lS == k || lS == c0 || lS == c1) ? kNoLabel : lS;
+    int c3 = (lW < 0 || lW == k || lW == c0 || lW == c1 || lW == c2) ? kNoLabel : lW;
+    // sorting network on four values
+#define SEEDS_CSWAP(a, b)              \
+    {                                  \
+        const int lo = min(a, b);      \
+        b = max(a, b);                 \
+        a = lo;                        \
+    }
+    SEEDS_CSWAP(c0, c1) SEEDS_CSWAP(c2, c3) SEEDS_CSWAP(c0, c2) SEEDS_CSWAP(c1, c3)
+    SEEDS_CSWAP(c1, c2)
+#undef SEEDS_CSWAP
+    nb.cand[0] = c0;
+    nb.cand[1] = c1;
+    nb.cand[2] = c2;
+    nb.cand[3] = c3;
+    const int nc = (c0 != kNoLabel) + (c1 != kNoLabel) + (c2 != kNoLabel) + (c3 != kNoLabel);
+    nb.nc = nc;
+    nb.movable = nc > 0 && ring_keeps_connected(r);
+    return nb;
+}
+
+// Segment-wide sum over SEG consecutive lanes of a wavefront (SEG <= 64).
+template <int SEG>
+__device__ __forceinline__ int64_t segment_sum(int64_t v) {
+#pragma unroll
+    for (int off = SEG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SEG);
+    return v;
+}
+
+// Pixel level, boundary term (Prop. 2): W_x weighs label x over the 5x5
+// window around p by how many in-image 3x3 patches centred on p's 3x3
+// neighbours contain the cell; per axis that is
+// |([p-1, p+1] clipped to the image) n [q-1, q+1]| for cell coordinate q.
+__device__ __forceinline__ int axis_weight(int p, int q, int n) {
+    if (q < 0 || q >= n) return 0;
+    const int lo = max(max(p - 1, 0), q - 1), hi = min(min(p + 1, n - 1), q + 1);
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
+
+// Pixel level decision for pixel (x, y) from the state in lab / hist:
+// best 4-neighbour label n of the gain
+//   g = (h_n(j) - h_k(j) + 1) + gamma (W_n + |K_p| - W_k)
+// (colour part: Prop. 1 with one look-up per side; boundary part: Prop. 2),
+// ties to the smaller label, taken only if g > 0.
+struct PixelMove {
+    int n;  // target label, -1 for no move
+    int k;  // current label
+    int j;  // colour bin of the pixel
+};
+
+__device__ __forceinline__ PixelMove pixel_decision(const Dims &d, const int32_t *__restrict__ lab,
+                                                    const uint8_t *__restrict__ bins,
+                                                    const int32_t *__restrict__ hist, int x,
+                                                    int y) {
+    PixelMove mv;
+    const Neighbourhood nb = neighbourhood(lab, d.W, d.H, x, y);
+    mv.k = nb.k;
+    mv.n = -1;
+    mv.j = 0;
+    if (!nb.movable) return mv;
+    const int k = nb.k;
+    const int j = bins[(int64_t)y * d.W + x];
+    mv.j = j;
+    const int hk = hist[(int64_t)k * d.hs + j];
+    int g[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        g[c] = c < nb.nc ? hist[(int64_t)nb.cand[c] * d.hs + j] - hk + 1 : INT32_MIN / 2;
+    if (d.gamma) {
+        int wk = 0, wn[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            const int wy = axis_weight(y, y + dy, d.H);
+            if (!wy) continue;
+#pragma unroll
+            for (int dx = -2; dx <= 2; ++dx) {
+                const int wx = axis_weight(x, x + dx, d.W);
+                if (!wx) continue;
+                const int l = lab[(int64_t)(y + dy) * d.W + x + dx];
+                const int w = wx * wy;
+                wk += l == k ? w : 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wn[c] += l == nb.cand[c] ? w : 0;
+            }
+        }
+        const int kp = (min(x + 1, d.W - 1) - max(x - 1, 0) + 1) *
+                       (min(y + 1, d.H - 1) - max(y - 1, 0) + 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nb.nc) g[c] += d.gamma * (wn[c] + kp - wk);
+    }
+    // candidates are ascending, so a strict ">" keeps the smaller label on ties
+    int bg = g[0], bn = nb.cand[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+        if (c < nb.nc && g[c] > bg) {
+            bg = g[c];
+            bn = nb.cand[c];
+        }
+    mv.n = bg > 0 ? bn : -1;
+    return mv;
+}
+
+}  // namespace seeds

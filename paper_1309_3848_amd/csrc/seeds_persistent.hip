@@ -1,0 +1,188 @@
+// Persistent refinement kernel: one cooperative launch runs the whole
+// schedule (every phase of every level and the level transitions) with
+// grid-wide barriers between phases.
+//
+// Phase snapshot without a second barrier. Units of one class are at least
+// three units apart, so a decision never reads a label that another decision
+// of the same phase writes: labels are written in place as soon as a move is
+// taken. The colour histograms and sizes exist twice. Phase t reads copy
+// t % 2 (the state after phase t-1) and adds its deltas to the other copy,
+// which holds the state after phase t-2; each workgroup also re-applies the
+// deltas it logged in phase t-1 to that copy. After the barrier the other
+// copy holds the state after phase t. At the end of the launch the last
+// phase's deltas are re-applied to the stale copy, so both copies are equal
+// again between launches.
+//
+// Under the exact block rule a block phase needs the drop rule (a move k -> n
+// is dropped when n is a source in the same phase), which is only known once
+// every decision of the phase is made: those phases decide, synchronise,
+// then filter and apply, and synchronise again.
+#include "seeds_phase.h"
+
+namespace seeds {
+namespace {
+
+constexpr int kSpinLimit = 1 << 22;  // about a second of waiting: then give up
+
+// Grid-wide barrier. The last workgroup to arrive resets the arrival count
+// and bumps the generation; the others wait for the generation to change.
+// The arrival is acquire-release and the wait an acquire, both at device
+// scope, so every write before the barrier is visible after it. A wait that
+// exceeds kSpinLimit sets the error flag and makes every workgroup return.
+__device__ bool grid_sync(uint32_t *sync, uint32_t &gen) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const uint32_t old =
+            __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    __hip_atomic_store(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        ++gen;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok;
+}
+
+template <bool BIG>
+__global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
+    extern __shared__ uint8_t sbin[];
+    __shared__ int s_logn[2];
+    const Dims &d = a.d;
+    uint32_t gen = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) s_logn[0] = s_logn[1] = 0;
+    __syncthreads();
+    int4 *const log0 = a.log + (int64_t)blockIdx.x * a.log_cap;
+    int4 *const log1 = a.log + ((int64_t)gridDim.x + blockIdx.x) * a.log_cap;
+    Sched sc = a.start;
+    int cur_bl = a.cur_bl;
+    int par = 0;          // histogram copy holding the current state
+    int phases = 0;
+    uint32_t stamp = a.stamp;
+    for (;;) {
+        int cls = 0;
+        const SchedOp op = sched_next(d, sc, a.max_phases < 0 ? -1 : a.max_phases - phases, &cls);
+        if (op == OP_END) break;
+        if (op == OP_DESCEND) {
+            descend(a, sc.level, cur_bl);
+            if (sc.level > 1) cur_bl ^= 1;
+            if (!grid_sync(a.sync, gen)) return;
+        } else {
+            // bring the write copy up to date with this workgroup's previous phase
+            int32_t *hW = pick(a.hist, par ^ 1);
+            int32_t *sW = pick(a.size, par ^ 1);
+            int4 *cur_log = par ? log1 : log0;
+            const int4 *prev_log = par ? log0 : log1;
+            int *cur_n = par ? &s_logn[1] : &s_logn[0];
+            const int prev_n = par ? s_logn[0] : s_logn[1];
+            if (phases > 0) replay(a, prev_log, min(prev_n, a.log_cap), hW, sW);
+            __syncthreads();
+            if (threadIdx.x == 0) *cur_n = 0;
+            __syncthreads();
+            ++stamp;
+            if (sc.level == 0) {
+                pixel_phase(a, cls, par, cur_log, cur_n);
+            } else {
+                int32_t *units = pick(a.bl, cur_bl);
+                if (d.rule == SEEDS_BLOCK_EXACT) {
+                    block_phase_any<BIG>(a, sc.level, cls, par, 1, stamp, units, sbin, cur_log, cur_n);
+                    if (!grid_sync(a.sync, gen)) return;
+                    block_phase_any<BIG>(a, sc.level, cls, par, 2, stamp, units, sbin, cur_log, cur_n);
+                } else {
+                    block_phase_any<BIG>(a, sc.level, cls, par, 0, stamp, units, sbin, cur_log, cur_n);
+                }
+            }
+            if (!grid_sync(a.sync, gen)) return;
+            par ^= 1;
+            ++phases;
+        }
+        sched_done(sc, op);
+    }
+    // the copy read by the last phase lacks that phase's deltas
+    if (phases > 0)
+        replay(a, par ? log0 : log1, min(par ? s_logn[0] : s_logn[1], a.log_cap),
+               pick(a.hist, par ^ 1), pick(a.size, par ^ 1));
+}
+
+}  // namespace
+
+PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu) {
+    PersistentGeom g;
+    int ppl_max = 1;
+    for (int l = 1; l < d.L; ++l) ppl_max = max(ppl_max, seg_ppl(l));
+    g.lds_bytes = kPT * ppl_max;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus < 1)
+        cus = 1;
+    int occ = 0;
+    const void *fn = d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kPT, g.lds_bytes) != hipSuccess ||
+        occ < 1)
+        occ = 1;
+    int groups = cus * min(occ, max(1, groups_per_cu));
+    // no more groups than one round of the busiest level needs
+    int useful = 1;
+    for (int l = 0; l < d.L; ++l) {
+        const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
+        const int n = class_cols(units_w(d, l), 0) * class_rows(units_h(d, l), 0);
+        useful = max(useful, (n + per_group - 1) / per_group);
+    }
+    g.groups = max(1, min(groups, useful));
+    int cap = 1;
+    for (int l = 0; l < d.L; ++l) {
+        const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
+        const int n = class_cols(units_w(d, l), 0) * class_rows(units_h(d, l), 0);
+        const int rounds = (n + g.groups * per_group - 1) / (g.groups * per_group);
+        const int entries = l == 0 ? 1 : min(1 << (2 * l), d.nb);
+        cap = max(cap, rounds * per_group * entries);
+    }
+    g.log_cap = cap;
+    return g;
+}
+
+hipError_t launch_refine(const Dims &d, const Buffers &b, const PersistentGeom &g,
+                         const Sched &start, int cur_bl, int max_phases, uint32_t stamp,
+                         hipStream_t s) {
+    RefineArgs a;
+    a.d = d;
+    a.bins = b.bins;
+    a.lab = b.lab;
+    a.bl[0] = b.bl[0];
+    a.bl[1] = b.bl[1];
+    a.hist[0] = b.hist[0];
+    a.hist[1] = b.hist[1];
+    a.size[0] = b.size[0];
+    a.size[1] = b.size[1];
+    a.src = b.src;
+    a.pend = b.pend;
+    a.log = b.log;
+    a.log_n = b.log_n;
+    a.log_cap = g.log_cap;
+    a.log_groups = g.groups;
+    a.sync = b.sync;
+    a.start = start;
+    a.cur_bl = cur_bl;
+    a.max_phases = max_phases;
+    a.stamp = stamp;
+    void *args[] = {&a};
+    const void *fn = d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    return hipLaunchCooperativeKernel(fn, dim3(g.groups), dim3(kPT), args, (unsigned)g.lds_bytes,
+                                      s);
+}
+
+}  // namespace seeds

@@ -21,6 +21,9 @@ SEEDS_E_DEVICE = -3
 SEEDS_E_STATE = -4
 SEEDS_BLOCK_INTERSECT = 0
 SEEDS_BLOCK_EXACT = 1
+SEEDS_LAUNCH_GRAPH = 0
+SEEDS_LAUNCH_STEPS = 1
+SEEDS_LAUNCH_PERSISTENT = 2
 
 
 class SeedsError(RuntimeError):
@@ -57,6 +60,8 @@ def lib() -> ctypes.CDLL:
             "seeds_num_superpixels": ([P], I32),
             "seeds_histograms": ([P, P, P, I32, P], S),
             "seeds_level": ([P], I32),
+            "seeds_set_launch_mode": ([P, I32], S),
+            "seeds_sync": ([P, P], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -151,6 +156,14 @@ def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, 
                                   size.data_ptr() if size is not None else None,
                                   1 if host else 0, _stream(stream)))
     return hist, size
+
+
+def seeds_set_launch_mode(ctx, mode: int) -> None:
+    _check(lib().seeds_set_launch_mode(ctx, mode))
+
+
+def seeds_sync(ctx, stream=None) -> None:
+    _check(lib().seeds_sync(ctx, _stream(stream)))
 
 
 def seeds_destroy(ctx) -> None:

@@ -30,11 +30,20 @@ def S():
     return seeds
 
 
-def _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases=-1):
+MODES = {"graph": 0, "steps": 1, "persistent": 2}
+
+
+@pytest.fixture(params=list(MODES))
+def mode(request):
+    return MODES[request.param]
+
+
+def _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases=-1, mode=0):
     import torch
     rgb = torch.from_numpy(np.ascontiguousarray(img)).cuda()
     ctx = S.seeds_init(rgb, K, S.make_params(L, B, I, gamma, rule))
     try:
+        S.seeds_set_launch_mode(ctx, mode)
         if max_phases < 0:
             S.seeds_refine(ctx)
         else:
@@ -45,15 +54,16 @@ def _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases=-1):
         hist = torch.empty((keff, B ** 3), dtype=torch.int32)
         size = torch.empty((keff,), dtype=torch.int32)
         S.seeds_histograms(ctx, hist, size)
+        S.seeds_sync(ctx)
         return lab.cpu().numpy(), hist.numpy(), size.numpy(), S.seeds_level(ctx)
     finally:
         S.seeds_destroy(ctx)
 
 
-def _compare(S, img, K, L, B=5, I=4, gamma=1, rule=0, max_phases=-1, check_valid=True):
+def _compare(S, img, K, L, B=5, I=4, gamma=1, rule=0, max_phases=-1, check_valid=True, mode=0):
     _say(f"shape={img.shape[:2]} K={K} L={L} B={B} I={I} gamma={gamma} rule={rule} "
-         f"max_phases={max_phases}")
-    lab, hist, size, level = _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases)
+         f"max_phases={max_phases} mode={mode}")
+    lab, hist, size, level = _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases, mode)
     ref_lab, ref_hist, ref_size = oracle.seeds(img, K, L, B, I, gamma, rule, max_phases)
     assert lab.shape == ref_lab.shape
     bad = np.argwhere(lab != ref_lab)
@@ -70,24 +80,26 @@ def _compare(S, img, K, L, B=5, I=4, gamma=1, rule=0, max_phases=-1, check_valid
 
 # --------------------------------------------------------------------------
 
-def test_small_image_full_schedule(S):
+def test_small_image_full_schedule(S, mode):
     from paper_1309_3848_amd import synth
     img = synth.voronoi_image(97, 131, 12, 8.0, seed=7)
-    _compare(S, img, K=40, L=3, B=5, I=2)
+    _compare(S, img, K=40, L=3, B=5, I=2, mode=mode)
 
 
-def test_481x321_workload(S):
+def test_481x321_workload(S, mode):
     from paper_1309_3848_amd import synth
-    _compare(S, synth.single_481x321(), K=200, L=3, B=5, I=4, gamma=1)
+    _compare(S, synth.single_481x321(), K=200, L=3, B=5, I=4, gamma=1, mode=mode)
 
 
-def test_1080p_workload(S):
+@pytest.mark.parametrize("rule", [0, 1])
+def test_1080p_workload(S, mode, rule):
     from paper_1309_3848_amd import synth
-    _compare(S, synth.single_1080p(), K=1000, L=4, B=5, I=4, gamma=1, check_valid=False)
+    _compare(S, synth.single_1080p(), K=1000, L=4, B=5, I=4, gamma=1, rule=rule,
+             check_valid=False, mode=mode)
 
 
 @pytest.mark.parametrize("case", range(16))
-def test_random_configurations(S, case):
+def test_random_configurations(S, case, mode):
     from paper_1309_3848_amd import synth
     rng = np.random.default_rng(500 + case)
     while True:
@@ -104,46 +116,74 @@ def test_random_configurations(S, case):
     rule = int(rng.integers(0, 2))
     img = synth.voronoi_image(H, W, int(rng.integers(3, 40)), float(rng.uniform(2, 16)),
                               seed=600 + case)
-    _compare(S, img, K, L, B, I, gamma, rule)
+    _compare(S, img, K, L, B, I, gamma, rule, mode=mode)
 
 
 @pytest.mark.parametrize("rule", [0, 1])
-def test_every_phase_matches(S, rule):
+def test_every_phase_matches(S, rule, mode):
     """Stop after 0, 1, 2, ... phases: the state (at whatever level) matches."""
     from paper_1309_3848_amd import synth
     img = synth.voronoi_image(75, 103, 10, 8.0, seed=31)
     total = 3 * 2 * 9
     for n in range(0, total + 1):
         _compare(S, img, K=30, L=3, B=4, I=2, gamma=1, rule=rule, max_phases=n,
-                 check_valid=(n % 9 == 0))
+                 check_valid=(n % 9 == 0), mode=mode)
 
 
 @pytest.mark.parametrize("H,W,K,L", [
     (1, 1, 1, 1), (2, 2, 1, 2), (1, 57, 3, 1), (57, 1, 3, 1), (3, 200, 5, 2), (200, 3, 5, 2),
     (16, 16, 1, 5), (33, 65, 2, 1), (64, 64, 64, 3),
 ])
-def test_edge_shapes(S, H, W, K, L):
+def test_edge_shapes(S, H, W, K, L, mode):
     from paper_1309_3848_amd import synth
     img = synth.voronoi_image(H, W, 4, 8.0, seed=H * 1000 + W)
-    _compare(S, img, K, L, B=5, I=3, gamma=1)
+    _compare(S, img, K, L, B=5, I=3, gamma=1, mode=mode)
 
 
-def test_flat_and_two_colour_images(S):
+def test_flat_and_two_colour_images(S, mode):
     img = np.full((64, 96, 3), 140, np.uint8)
-    _compare(S, img, 24, 4, 5, 3, 0)
+    _compare(S, img, 24, 4, 5, 3, 0, mode=mode)
     img = np.zeros((32, 64, 3), np.uint8)
     img[:, :35] = (200, 40, 40)
     img[:, 35:] = (30, 30, 220)
-    lab = _compare(S, img, 2, 3, 5, 12, 1)
+    lab = _compare(S, img, 2, 3, 5, 12, 1, mode=mode)
     assert np.array_equal(lab, (np.arange(64)[None, :] >= 35).astype(np.int32).repeat(32, 0))
 
 
-def test_largest_block_sizes(S):
+def test_largest_block_sizes(S, mode):
     """levels = 8: blocks of side 128, 64, 32, 16 use the multi-pixel-per-lane path."""
     from paper_1309_3848_amd import synth
     img = synth.voronoi_image(300, 530, 20, 8.0, seed=77)
-    _compare(S, img, 4, 8, 5, 1, 1)
-    _compare(S, img, 4, 8, 3, 2, 1, rule=1)
+    _compare(S, img, 4, 8, 5, 1, 1, mode=mode)
+    _compare(S, img, 4, 8, 3, 2, 1, rule=1, mode=mode)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_alternating_launch_modes(S, rule):
+    """Phases run alternately by the persistent kernel and by per-step
+    launches: both keep the two histogram copies equal between calls."""
+    import torch
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(110, 150, 14, 8.0, seed=91)
+    rgb = torch.from_numpy(img).cuda()
+    ctx = S.seeds_init(rgb, 36, S.make_params(3, 5, 3, 1, rule))
+    o = oracle.Oracle(img, 36, 3, 5, 3, 1, rule)
+    try:
+        for i, n in enumerate([5, 4, 9, 1, 13, 2, 30, 100]):
+            S.seeds_set_launch_mode(ctx, i % 3)
+            _say(f"alternating step {i}: {n} phases mode {i % 3}")
+            S.seeds_refine_phases(ctx, n)
+            o.run(n)
+            lab = torch.empty((110, 150), dtype=torch.int32)
+            S.seeds_labels(ctx, lab)
+            hist = torch.empty((o.K, 125), dtype=torch.int32)
+            size = torch.empty((o.K,), dtype=torch.int32)
+            S.seeds_histograms(ctx, hist, size)
+            rh, rs = o.histograms()
+            assert np.array_equal(lab.numpy(), o.labels())
+            assert np.array_equal(hist.numpy(), rh) and np.array_equal(size.numpy(), rs)
+    finally:
+        S.seeds_destroy(ctx)
 
 
 def test_determinism_and_repeat_refine(S):
@@ -203,3 +243,37 @@ def test_strided_rows(S):
         S.seeds_destroy(ctx)
     ref, _, _ = oracle.seeds(img, 20, 2, 5, 2, 1, 0)
     assert np.array_equal(lab.numpy(), ref)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_graph_replays(S, rule):
+    """The refinement graph is captured on the first refine and replayed by
+    later ones (after reinit, and for the pixel-only second refine), with
+    eager work and synchronisations in between; every replay must equal the
+    oracle."""
+    import torch
+    from paper_1309_3848_amd import synth
+    imgs = [synth.voronoi_image(100, 140, 12, 8.0, seed=200 + i) for i in range(3)]
+    ctx = S.seeds_init(torch.from_numpy(imgs[0]).cuda(), 40, S.make_params(3, 5, 2, 1, rule))
+    try:
+        S.seeds_set_launch_mode(ctx, S.SEEDS_LAUNCH_GRAPH)
+        for rep in range(6):
+            img = imgs[rep % 3]
+            _say(f"graph replay {rep}")
+            S.seeds_reinit(ctx, torch.from_numpy(img).cuda())
+            S.seeds_refine(ctx)
+            junk = torch.randn(256, 256, device="cuda") @ torch.randn(256, 256, device="cuda")
+            torch.cuda.synchronize()
+            S.seeds_refine(ctx)  # pixel-only sweeps: a second cached graph
+            lab = torch.empty((100, 140), dtype=torch.int32)
+            S.seeds_labels(ctx, lab)
+            hist = torch.empty((S.seeds_num_superpixels(ctx), 125), dtype=torch.int32)
+            S.seeds_histograms(ctx, hist, None)
+            o = oracle.Oracle(img, 40, 3, 5, 2, 1, rule)
+            o.run()
+            o.run()
+            assert np.array_equal(lab.numpy(), o.labels()), rep
+            assert np.array_equal(hist.numpy(), o.histograms()[0]), rep
+            del junk
+    finally:
+        S.seeds_destroy(ctx)
