@@ -130,7 +130,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Layout of the context's single device allocation. The two histogram
 // copies are contiguous, and so are the two size copies.
 struct Layout {
-    size_t bins, lab, bl0, bl1, hist, size, src, pend, log, log_n, sync, total;
+    size_t bins, lab, bl0, bl1, hist, src, pend, log, log_n, sync, total;
 };
 
 Layout layout_of(const Dims &d, const PersistentGeom &g, int phase_groups_, int phase_cap) {
@@ -143,12 +143,11 @@ Layout layout_of(const Dims &d, const PersistentGeom &g, int phase_groups_, int 
     l.lab = off;  off += align_up(N * 4);
     l.bl0 = off;  off += align_up(blk * 4);
     l.bl1 = off;  off += align_up(blk * 4);
-    l.hist = off; off += align_up(2 * (size_t)d.K * d.hs * 4);
-    l.size = off; off += align_up(2 * (size_t)d.K * 4);
+    l.hist = off; off += align_up(2 * ((size_t)d.K * d.hs + d.K) * 4);
     l.src = off;  off += align_up((size_t)d.K * 4);
     l.pend = off; off += align_up(pend * 4);
     const size_t entries = std::max((size_t)g.groups * g.log_cap, (size_t)phase_groups_ * phase_cap);
-    l.log = off;  off += align_up(2 * entries * 16);
+    l.log = off;  off += align_up(2 * entries * 8);
     l.log_n = off; off += align_up(2 * (size_t)std::max(g.groups, phase_groups_) * 4);
     l.sync = off; off += align_up(4 * 4);
     l.total = off;
@@ -408,12 +407,12 @@ seeds_status seeds_init(seeds_ctx **out, const uint8_t *rgb, int32_t H, int32_t 
     ctx->b.bl[0] = (int32_t *)(base + l.bl0);
     ctx->b.bl[1] = (int32_t *)(base + l.bl1);
     ctx->b.hist[0] = (int32_t *)(base + l.hist);
-    ctx->b.hist[1] = ctx->b.hist[0] + (size_t)d.K * d.hs;
-    ctx->b.size[0] = (int32_t *)(base + l.size);
-    ctx->b.size[1] = ctx->b.size[0] + d.K;
+    ctx->b.hist[1] = ctx->b.hist[0] + (size_t)d.K * d.hs + d.K;
+    ctx->b.size[0] = ctx->b.hist[0] + (size_t)d.K * d.hs;
+    ctx->b.size[1] = ctx->b.hist[1] + (size_t)d.K * d.hs;
     ctx->b.src = (int32_t *)(base + l.src);
     ctx->b.pend = (int32_t *)(base + l.pend);
-    ctx->b.log = (int4 *)(base + l.log);
+    ctx->b.log = (int2 *)(base + l.log);
     ctx->b.log_n = (int32_t *)(base + l.log_n);
     ctx->b.sync = (uint32_t *)(base + l.sync);
     ctx->stamp = 0;
@@ -517,8 +516,9 @@ seeds_status seeds_histograms(const seeds_ctx *cctx, int32_t *hist, int32_t *siz
     hipStream_t s = (hipStream_t)hip_stream;
     const Dims &d = ctx->d;
     const hipMemcpyKind kind = out_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    hipError_t e = hipSuccess;
-    if (hist)
+    // pixel phases do not maintain the sizes: derive them from the histograms
+    hipError_t e = launch_sizes(d, ctx->b, s);
+    if (e == hipSuccess && hist)
         e = hipMemcpy2DAsync(hist, (size_t)d.nb * 4, ctx->b.hist[0], (size_t)d.hs * 4,
                              (size_t)d.nb * 4, d.K, kind, s);
     if (e == hipSuccess && size)

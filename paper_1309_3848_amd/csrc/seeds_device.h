@@ -33,21 +33,11 @@ __device__ __forceinline__ bool ring_keeps_connected(uint32_t r) {
     return __popc(starts) - __popc(lone_corners) == 1;
 }
 
-__device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict__ units, int uw,
-                                                       int uh, int ux, int uy) {
+// Neighbourhood from the labels of the unit and its 8-ring (-1 outside).
+__device__ __forceinline__ Neighbourhood neighbourhood9(int k, int lN, int lNE, int lE, int lSE,
+                                                        int lS, int lSW, int lW, int lNW) {
     Neighbourhood nb;
-    const int64_t row = (int64_t)uy * uw;
-    nb.k = units[row + ux];
-    const bool hasN = uy > 0, hasS = uy + 1 < uh, hasW = ux > 0, hasE = ux + 1 < uw;
-    const int lN = hasN ? units[row - uw + ux] : -1;
-    const int lS = hasS ? units[row + uw + ux] : -1;
-    const int lW = hasW ? units[row + ux - 1] : -1;
-    const int lE = hasE ? units[row + ux + 1] : -1;
-    const int lNE = hasN && hasE ? units[row - uw + ux + 1] : -1;
-    const int lSE = hasS && hasE ? units[row + uw + ux + 1] : -1;
-    const int lSW = hasS && hasW ? units[row + uw + ux - 1] : -1;
-    const int lNW = hasN && hasW ? units[row - uw + ux - 1] : -1;
-    const int k = nb.k;
+    nb.k = k;
     const uint32_t r = (lN == k) | (lNE == k) << 1 | (lE == k) << 2 | (lSE == k) << 3 |
                        (lS == k) << 4 | (lSW == k) << 5 | (lW == k) << 6 | (lNW == k) << 7;
     // edge neighbours, keeping the first occurrence of each other label
@@ -75,9 +65,32 @@ __device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict
     return nb;
 }
 
+__device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict__ units, int uw,
+                                                       int uh, int ux, int uy) {
+    const int64_t row = (int64_t)uy * uw;
+    const bool hasN = uy > 0, hasS = uy + 1 < uh, hasW = ux > 0, hasE = ux + 1 < uw;
+    const int k = units[row + ux];
+    const int lN = hasN ? units[row - uw + ux] : -1;
+    const int lS = hasS ? units[row + uw + ux] : -1;
+    const int lW = hasW ? units[row + ux - 1] : -1;
+    const int lE = hasE ? units[row + ux + 1] : -1;
+    const int lNE = hasN && hasE ? units[row - uw + ux + 1] : -1;
+    const int lSE = hasS && hasE ? units[row + uw + ux + 1] : -1;
+    const int lSW = hasS && hasW ? units[row + uw + ux - 1] : -1;
+    const int lNW = hasN && hasW ? units[row - uw + ux - 1] : -1;
+    return neighbourhood9(k, lN, lNE, lE, lSE, lS, lSW, lW, lNW);
+}
+
 // Segment-wide sum over SEG consecutive lanes of a wavefront (SEG <= 64).
 template <int SEG>
 __device__ __forceinline__ int64_t segment_sum(int64_t v) {
+#pragma unroll
+    for (int off = SEG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SEG);
+    return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ int32_t segment_sum32(int32_t v) {
 #pragma unroll
     for (int off = SEG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SEG);
     return v;
@@ -93,6 +106,24 @@ __device__ __forceinline__ int axis_weight(int p, int q, int n) {
     return hi >= lo ? hi - lo + 1 : 0;
 }
 
+
+// Pixel level, first test: is (x, y) a boundary pixel whose label stays
+// connected without it? Only the 3x3 neighbourhood is read.
+__device__ __forceinline__ bool pixel_movable(const Dims &d, const int32_t *__restrict__ lab, int x,
+                                              int y) {
+    int r3[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int yy = y + dy, xx = x + dx;
+            r3[dy + 1][dx + 1] =
+                (yy >= 0 && yy < d.H && xx >= 0 && xx < d.W) ? lab[(int64_t)yy * d.W + xx] : -1;
+        }
+    return neighbourhood9(r3[1][1], r3[0][1], r3[0][2], r3[1][2], r3[2][2], r3[2][1], r3[2][0],
+                          r3[1][0], r3[0][0])
+        .movable;
+}
 
 // Pixel level decision for pixel (x, y) from the state in lab / hist:
 // best 4-neighbour label n of the gain
@@ -110,14 +141,28 @@ __device__ __forceinline__ PixelMove pixel_decision(const Dims &d, const int32_t
                                                     const int32_t *__restrict__ hist, int x,
                                                     int y) {
     PixelMove mv;
-    const Neighbourhood nb = neighbourhood(lab, d.W, d.H, x, y);
-    mv.k = nb.k;
     mv.n = -1;
-    mv.j = 0;
+    // every label the decision needs, loaded at once (-1 outside the image):
+    // the 3x3 ring, and with the boundary term the whole 5x5 window
+    const int R = d.gamma ? 2 : 1;
+    int win[5][5];
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int yy = y + dy, xx = x + dx;
+            const bool need = (dy >= -R && dy <= R && dx >= -R && dx <= R);
+            win[dy + 2][dx + 2] = (need && yy >= 0 && yy < d.H && xx >= 0 && xx < d.W)
+                                      ? lab[(int64_t)yy * d.W + xx]
+                                      : -1;
+        }
+    const int j = bins[(int64_t)y * d.W + x];
+    const Neighbourhood nb = neighbourhood9(win[2][2], win[1][2], win[1][3], win[2][3], win[3][3],
+                                            win[3][2], win[3][1], win[2][1], win[1][1]);
+    mv.k = nb.k;
+    mv.j = j;
     if (!nb.movable) return mv;
     const int k = nb.k;
-    const int j = bins[(int64_t)y * d.W + x];
-    mv.j = j;
     const int hk = hist[(int64_t)k * d.hs + j];
     int g[4];
 #pragma unroll
@@ -128,13 +173,10 @@ __device__ __forceinline__ PixelMove pixel_decision(const Dims &d, const int32_t
 #pragma unroll
         for (int dy = -2; dy <= 2; ++dy) {
             const int wy = axis_weight(y, y + dy, d.H);
-            if (!wy) continue;
 #pragma unroll
             for (int dx = -2; dx <= 2; ++dx) {
-                const int wx = axis_weight(x, x + dx, d.W);
-                if (!wx) continue;
-                const int l = lab[(int64_t)(y + dy) * d.W + x + dx];
-                const int w = wx * wy;
+                const int w = wy * axis_weight(x, x + dx, d.W);
+                const int l = win[dy + 2][dx + 2];
                 wk += l == k ? w : 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) wn[c] += l == nb.cand[c] ? w : 0;

@@ -74,12 +74,13 @@ struct Buffers {
     uint8_t *bins;     // H*W colour bin of every pixel
     int32_t *lab;      // H*W pixel labels (valid at level 0)
     int32_t *bl[2];    // block-label grids, ping-pong (levels >= 1)
-    int32_t *hist[2];  // K*hs colour histograms in pixel counts (two equal copies
-                       // between launches; the persistent kernel alternates them)
-    int32_t *size[2];  // K superpixel sizes (same two copies)
+    int32_t *hist[2];  // state copy c: K*hs colour-histogram cells in pixel counts,
+                       // immediately followed by the K superpixel sizes; the two
+                       // copies are equal between launches and alternate in phases
+    int32_t *size[2];  // = hist[c] + K*hs
     int32_t *src;      // K phase stamps of move sources (exact rule's drop rule)
     int32_t *pend;     // one decision per class unit: target label or -1
-    int4 *log;         // per-workgroup move logs, 2 parities x groups x cap entries
+    int2 *log;         // per-workgroup delta logs, 2 parities x groups x cap (index, delta)
     int32_t *log_n;    // per-phase launches: entries in each log, 2 x groups
     uint32_t *sync;    // persistent kernel: barrier count, generation, error flag
 };
@@ -110,6 +111,7 @@ hipError_t launch_phase_kernel(const Dims &d, const Buffers &b, int log_groups, 
                                int level, int cls, int par, int pass, uint32_t stamp, int cur_bl,
                                int replay_groups, hipStream_t s);
 int phase_groups(const Dims &d, int level, int cls);
+hipError_t launch_sizes(const Dims &d, const Buffers &b, hipStream_t s);
 void phase_log_shape(const Dims &d, int *groups, int *cap);
 hipError_t launch_refine(const Dims &d, const Buffers &b, const PersistentGeom &g,
                          const Sched &start, int cur_bl, int max_phases, uint32_t stamp,

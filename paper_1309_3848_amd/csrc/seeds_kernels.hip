@@ -130,10 +130,9 @@ hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_init(const Dims &d, const Buffers &b, const uint8_t *rgb, int64_t pitch,
                        int32_t *top_labels, hipStream_t s) {
-    // the two histogram copies and the two size copies are contiguous
-    hipError_t e = launch_fill(b.hist[0], 0, 2 * (int64_t)d.K * d.hs, s);
+    // the two state copies (histograms, then sizes) are contiguous
+    hipError_t e = launch_fill(b.hist[0], 0, 2 * ((int64_t)d.K * d.hs + d.K), s);
     if (e != hipSuccess) return e;
-    if ((e = launch_fill(b.size[0], 0, 2 * (int64_t)d.K, s)) != hipSuccess) return e;
     const unsigned tiles = blocks_for(d.W, kInitTW) * blocks_for(d.H, kInitTH);
     hipLaunchKernelGGL(k_init, dim3(tiles), dim3(kThreads), 0, s, d, rgb, pitch, b.bins, top_labels,
                        b.hist[0], b.size[0], b.hist[1], b.size[1]);

@@ -61,16 +61,17 @@ __device__ bool grid_sync(uint32_t *sync, uint32_t &gen) {
 template <bool BIG>
 __global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
     extern __shared__ uint8_t sbin[];
-    __shared__ int s_logn[2];
+    __shared__ DeltaTable t;
+    __shared__ PixelList pl;
+    __shared__ int s_prev_n;
     const Dims &d = a.d;
     uint32_t gen = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x == 0) s_logn[0] = s_logn[1] = 0;
-    __syncthreads();
-    int4 *const log0 = a.log + (int64_t)blockIdx.x * a.log_cap;
-    int4 *const log1 = a.log + ((int64_t)gridDim.x + blockIdx.x) * a.log_cap;
+    int2 *const log0 = a.log + (int64_t)blockIdx.x * a.log_cap;
+    int2 *const log1 = a.log + ((int64_t)gridDim.x + blockIdx.x) * a.log_cap;
+    if (threadIdx.x == 0) s_prev_n = 0;
     Sched sc = a.start;
     int cur_bl = a.cur_bl;
-    int par = 0;          // histogram copy holding the current state
+    int par = 0;  // state copy holding the current state
     int phases = 0;
     uint32_t stamp = a.stamp;
     for (;;) {
@@ -82,30 +83,31 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
             if (sc.level > 1) cur_bl ^= 1;
             if (!grid_sync(a.sync, gen)) return;
         } else {
-            // bring the write copy up to date with this workgroup's previous phase
-            int32_t *hW = pick(a.hist, par ^ 1);
-            int32_t *sW = pick(a.size, par ^ 1);
-            int4 *cur_log = par ? log1 : log0;
-            const int4 *prev_log = par ? log0 : log1;
-            int *cur_n = par ? &s_logn[1] : &s_logn[0];
-            const int prev_n = par ? s_logn[0] : s_logn[1];
-            if (phases > 0) replay(a, prev_log, min(prev_n, a.log_cap), hW, sW);
+            int32_t *W = pick(a.state, par ^ 1);
+            int2 *cur_log = par ? log1 : log0;
+            const int2 *prev_log = par ? log0 : log1;
+            const int prev_n = s_prev_n;
+            table_clear(t);
             __syncthreads();
-            if (threadIdx.x == 0) *cur_n = 0;
-            __syncthreads();
+            // the previous phase's deltas, logged by this workgroup
+            if (phases > 0) replay(prev_log, min(prev_n, a.log_cap), W);
             ++stamp;
             if (sc.level == 0) {
-                pixel_phase(a, cls, par, cur_log, cur_n);
+                pixel_phase(a, cls, par, t, cur_log, pl);
             } else {
                 int32_t *units = pick(a.bl, cur_bl);
                 if (d.rule == SEEDS_BLOCK_EXACT) {
-                    block_phase_any<BIG>(a, sc.level, cls, par, 1, stamp, units, sbin, cur_log, cur_n);
+                    block_phase_any<BIG>(a, sc.level, cls, par, 1, stamp, units, sbin, t, cur_log);
                     if (!grid_sync(a.sync, gen)) return;
-                    block_phase_any<BIG>(a, sc.level, cls, par, 2, stamp, units, sbin, cur_log, cur_n);
+                    block_phase_any<BIG>(a, sc.level, cls, par, 2, stamp, units, sbin, t, cur_log);
                 } else {
-                    block_phase_any<BIG>(a, sc.level, cls, par, 0, stamp, units, sbin, cur_log, cur_n);
+                    block_phase_any<BIG>(a, sc.level, cls, par, 0, stamp, units, sbin, t, cur_log);
                 }
             }
+            __syncthreads();
+            table_flush(a, t, W, cur_log);
+            __syncthreads();
+            if (threadIdx.x == 0) s_prev_n = t.n;
             if (!grid_sync(a.sync, gen)) return;
             par ^= 1;
             ++phases;
@@ -113,9 +115,7 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
         sched_done(sc, op);
     }
     // the copy read by the last phase lacks that phase's deltas
-    if (phases > 0)
-        replay(a, par ? log0 : log1, min(par ? s_logn[0] : s_logn[1], a.log_cap),
-               pick(a.hist, par ^ 1), pick(a.size, par ^ 1));
+    if (phases > 0) replay(par ? log0 : log1, min(s_prev_n, a.log_cap), pick(a.state, par ^ 1));
 }
 
 }  // namespace
@@ -148,8 +148,7 @@ PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu)
         const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
         const int n = class_cols(units_w(d, l), 0) * class_rows(units_h(d, l), 0);
         const int rounds = (n + g.groups * per_group - 1) / (g.groups * per_group);
-        const int entries = l == 0 ? 1 : min(1 << (2 * l), d.nb);
-        cap = max(cap, rounds * per_group * entries);
+        cap = max(cap, rounds * deltas_per_round(d, l));
     }
     g.log_cap = cap;
     return g;
@@ -164,10 +163,8 @@ hipError_t launch_refine(const Dims &d, const Buffers &b, const PersistentGeom &
     a.lab = b.lab;
     a.bl[0] = b.bl[0];
     a.bl[1] = b.bl[1];
-    a.hist[0] = b.hist[0];
-    a.hist[1] = b.hist[1];
-    a.size[0] = b.size[0];
-    a.size[1] = b.size[1];
+    a.state[0] = b.hist[0];
+    a.state[1] = b.hist[1];
     a.src = b.src;
     a.pend = b.pend;
     a.log = b.log;

@@ -1,16 +1,23 @@
-// Phase machinery shared by the persistent kernel and the per-phase kernels:
+// Phase machinery shared by the per-phase kernels and the persistent kernel:
 // the pixel phase, the block phase (three passes) and the level transition,
-// all with grid-stride loops, plus the move logs that keep the two histogram
-// copies in step.
+// all with grid-stride loops, and the bookkeeping that keeps the two copies
+// of the colour histograms and sizes in step.
 //
 // Phase snapshot. Units of one class are at least three units apart, so a
 // decision never reads a label that another decision of the same phase
 // writes: labels are written in place as soon as a move is taken. The colour
-// histograms and sizes exist twice. Phase t reads copy t % 2 (the state after
-// phase t-1) and adds its deltas to the other copy, which holds the state
-// after phase t-2; the deltas of phase t-1, kept in move logs, are added to
-// that copy as well during phase t. Once phase t is complete the other copy
-// holds the state after phase t.
+// histograms and sizes ("state") exist twice. Phase t reads copy t % 2 (the
+// state after phase t-1) and adds its deltas to the other copy, which holds
+// the state after phase t-2; the deltas of phase t-1, kept in move logs, are
+// added to that copy during phase t as well. Once phase t is complete the
+// other copy holds the state after phase t.
+//
+// Deltas. Each workgroup sums the deltas of its moves in an LDS hash table
+// keyed by state index (histogram cell k * hs + j, or size K * hs + k), then
+// adds every non-zero sum to the write copy with one global atomic and logs
+// it as (index, delta). Neighbouring moves mostly share cells, so this cuts
+// the global atomics and the log. Pixel phases leave the sizes alone: only
+// the Prop. 1 block rule reads them, and pixel phases come last.
 #pragma once
 
 #include "seeds_device.h"
@@ -24,19 +31,18 @@ struct RefineArgs {
     const uint8_t *bins;
     int32_t *lab;
     int32_t *bl[2];
-    int32_t *hist[2];
-    int32_t *size[2];
+    int32_t *state[2];  // copy c: K * hs histogram cells, then K sizes
     int32_t *src;
     int32_t *pend;
-    int4 *log;       // move logs: [2 parities][log_groups][log_cap] entries (k, n, j, cnt)
-    int32_t *log_n;  // per-phase launches: entries in each log, [2][log_groups]
+    int2 *log;          // move logs: [2 parities][log_groups][log_cap] (index, delta)
+    int32_t *log_n;     // per-phase launches: entries in each log, [2][log_groups]
     int log_cap;
     int log_groups;
-    uint32_t *sync;  // [0] arrivals, [1] generation, [2] error flag
+    uint32_t *sync;     // persistent kernel: [0] arrivals, [1] generation, [2] error flag
     Sched start;
     int cur_bl;
     int max_phases;
-    uint32_t stamp;  // stamp of the phase before the first one of this launch
+    uint32_t stamp;     // stamp of the phase before the first one of the launch
 };
 
 // Pointer selection by a run-time index without indexing an array (which would
@@ -46,48 +52,162 @@ __device__ __forceinline__ T *pick(T *const (&two)[2], int i) {
     return i ? two[1] : two[0];
 }
 
-__device__ __forceinline__ void log_move(const RefineArgs &a, int4 *mylog, int *s_logn, int k,
-                                         int n, int j, int cnt) {
-    const int slot = atomicAdd(s_logn, 1);
+// ---------------------------------------------------------------------------
+// Per-workgroup delta table in LDS (open addressing, linear probing).
+constexpr int kTableBits = 11;
+constexpr int kTableSize = 1 << kTableBits;
+constexpr int kTableProbes = 64;
+constexpr int32_t kEmptyKey = -1;
+
+struct DeltaTable {
+    int32_t key[kTableSize];
+    int32_t val[kTableSize];
+    int n;  // log entries written by this workgroup in this phase
+};
+
+__device__ __forceinline__ void table_clear(DeltaTable &t) {
+    for (int i = threadIdx.x; i < kTableSize; i += kPT) {
+        t.key[i] = kEmptyKey;
+        t.val[i] = 0;
+    }
+    if (threadIdx.x == 0) t.n = 0;
+}
+
+__device__ __forceinline__ void log_append(const RefineArgs &a, DeltaTable &t, int2 *mylog,
+                                           int32_t idx, int32_t delta) {
+    const int slot = atomicAdd(&t.n, 1);
     if (slot < a.log_cap)
-        mylog[slot] = make_int4(k, n, j, cnt);
+        mylog[slot] = make_int2(idx, delta);
     else
         __hip_atomic_store(&a.sync[2], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Move cnt pixels of bin j from superpixel k to n in one histogram copy.
-__device__ __forceinline__ void move_counts(int32_t *hist, int32_t *size, int hs, int k, int n,
-                                            int j, int cnt) {
-    atomicAdd(&hist[(int64_t)n * hs + j], cnt);
-    atomicSub(&hist[(int64_t)k * hs + j], cnt);
-    atomicAdd(&size[n], cnt);
-    atomicSub(&size[k], cnt);
+// Add delta to state index idx. A full neighbourhood in the table sends the
+// delta straight to the write copy and the log.
+__device__ __forceinline__ void table_add(const RefineArgs &a, DeltaTable &t, int32_t *W,
+                                          int2 *mylog, int32_t idx, int32_t delta) {
+    uint32_t h = ((uint32_t)idx * 2654435761u) >> (32 - kTableBits);
+#pragma nounroll
+    for (int p = 0; p < kTableProbes; ++p, h = (h + 1) & (kTableSize - 1)) {
+        const int32_t prev = atomicCAS(&t.key[h], kEmptyKey, idx);
+        if (prev == kEmptyKey || prev == idx) {
+            atomicAdd(&t.val[h], delta);
+            return;
+        }
+    }
+    atomicAdd(&W[idx], delta);
+    log_append(a, t, mylog, idx, delta);
 }
 
-__device__ inline void replay(const RefineArgs &a, const int4 *entries, int n, int32_t *hist,
-                       int32_t *size) {
+// After the phase's moves (and a workgroup barrier): one global atomic and one
+// log entry per non-zero sum.
+__device__ __forceinline__ void table_flush(const RefineArgs &a, DeltaTable &t, int32_t *W,
+                                            int2 *mylog) {
+    for (int i = threadIdx.x; i < kTableSize; i += kPT) {
+        const int32_t k = t.key[i], v = t.val[i];
+        if (k == kEmptyKey || v == 0) continue;
+        atomicAdd(&W[k], v);
+        log_append(a, t, mylog, k, v);
+    }
+}
+
+__device__ __forceinline__ void replay(const int2 *entries, int n, int32_t *W) {
     for (int e = threadIdx.x; e < n; e += kPT) {
-        const int4 v = entries[e];
-        move_counts(hist, size, a.d.hs, v.x, v.y, v.z, v.w);
+        const int2 v = entries[e];
+        atomicAdd(&W[v.x], v.y);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Pixel phase: one thread per pixel of the class, grid-stride.
-__device__ inline void pixel_phase(const RefineArgs &a, int cls, int par, int4 *mylog, int *s_logn) {
+// Pixel phase, grid-stride over the pixels of the class. Most pixels are not
+// on a boundary, and a wavefront of neighbouring pixels nearly always holds
+// some that are: every thread first makes the cheap 3x3 test, the movable
+// pixels are packed into an LDS list (ballot + one LDS atomic per wavefront),
+// and dense wavefronts then evaluate the gains.
+struct PixelList {
+    int n;
+    int unit[kPT];
+};
+
+__device__ __forceinline__ void wave_append(PixelList &pl, bool take, int value) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(&pl.n, __popcll(m));
+    base = __shfl(base, __ffsll((unsigned long long)m) - 1);
+    if (take) pl.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
+}
+
+__device__ inline void pixel_phase(const RefineArgs &a, int cls, int par, DeltaTable &t,
+                                   int2 *mylog, PixelList &pl) {
     const Dims &d = a.d;
     const int ncx = class_cols(d.W, cls), ncy = class_rows(d.H, cls);
     const int n = ncx * ncy;
-    const int32_t *hR = pick(a.hist, par);
-    int32_t *hW = pick(a.hist, par ^ 1);
-    int32_t *sW = pick(a.size, par ^ 1);
-    for (int i = blockIdx.x * kPT + threadIdx.x; i < n; i += gridDim.x * kPT) {
-        const int x = cls % 3 + 3 * (i % ncx), y = cls / 3 + 3 * (i / ncx);
-        const PixelMove mv = pixel_decision(d, a.lab, a.bins, hR, x, y);
-        if (mv.n < 0) continue;
-        a.lab[(int64_t)y * d.W + x] = mv.n;
-        move_counts(hW, sW, d.hs, mv.k, mv.n, mv.j, 1);
-        log_move(a, mylog, s_logn, mv.k, mv.n, mv.j, 1);
+    const int32_t *hR = pick(a.state, par);
+    int32_t *W = pick(a.state, par ^ 1);
+    const int per_round = gridDim.x * kPT;
+    const int rounds = (n + per_round - 1) / per_round;
+    for (int r = 0; r < rounds; ++r) {
+        if (threadIdx.x == 0) pl.n = 0;
+        __syncthreads();
+        const int i = r * per_round + blockIdx.x * kPT + threadIdx.x;
+        bool take = false;
+        if (i < n) take = pixel_movable(d, a.lab, cls % 3 + 3 * (i % ncx), cls / 3 + 3 * (i / ncx));
+        wave_append(pl, take, i);
+        __syncthreads();
+        if ((int)threadIdx.x < pl.n) {
+            const int u = pl.unit[threadIdx.x];
+            const int x = cls % 3 + 3 * (u % ncx), y = cls / 3 + 3 * (u / ncx);
+            const PixelMove mv = pixel_decision(d, a.lab, a.bins, hR, x, y);
+            if (mv.n >= 0) {
+                a.lab[(int64_t)y * d.W + x] = mv.n;
+                table_add(a, t, W, mylog, mv.n * d.hs + mv.j, 1);
+                table_add(a, t, W, mylog, mv.k * d.hs + mv.j, -1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse block histogram with wavefront ballots, for blocks of at most 64
+// pixels (one pixel per lane, segments of SEG lanes inside one wavefront):
+// for the lane's bin j (0xFF = no pixel), cnt = h_l(j) of its segment's block
+// and first = the lane is the lowest one of its segment with that bin. One
+// round per distinct bin in the wavefront; no LDS, no barrier.
+template <int SEG>
+__device__ __forceinline__ void ballot_bins(int j, int &cnt, bool &first) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (SEG <= 16) {
+        // small segments: compare with each lane of the segment
+        const int me = lane & (SEG - 1);
+        cnt = 0;
+        first = j != 0xFF;
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) {
+            const int v = __shfl(j, q, SEG);
+            const bool same = v == j && j != 0xFF;
+            cnt += same;
+            first = first && !(same && q < me);
+        }
+        return;
+    }
+    const uint64_t seg_mask =
+        (SEG == 64 ? ~0ull : ((1ull << SEG) - 1)) << ((lane / SEG) * SEG);
+    uint64_t todo = __ballot(j != 0xFF);
+    cnt = 0;
+    first = false;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int v = __shfl(j, leader);
+        const uint64_t same = __ballot(j == v);
+        if (j == v) {
+            const uint64_t mine = same & seg_mask;
+            cnt = __popcll(mine);
+            first = __ffsll((unsigned long long)mine) - 1 == lane;
+        }
+        todo &= ~same;
     }
 }
 
@@ -99,8 +219,8 @@ __device__ inline void pixel_phase(const RefineArgs &a, int cls, int par, int4 *
 //   pass 2: exact rule, apply the recorded moves whose target is no source
 template <int SEG, int PPL>
 __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int par, int pass,
-                            uint32_t stamp, int32_t *units, uint8_t *sbin, int4 *mylog,
-                            int *s_logn) {
+                                   uint32_t stamp, int32_t *units, uint8_t *sbin, DeltaTable &t,
+                                   int2 *mylog) {
     constexpr int SEGS = kPT / SEG;
     constexpr int NPX = SEG * PPL;
     const Dims &d = a.d;
@@ -111,12 +231,13 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
     const int per_round = gridDim.x * SEGS;
     const int rounds = (nunits + per_round - 1) / per_round;
     const int seg = threadIdx.x / SEG, lane = threadIdx.x % SEG;
-    const int32_t *hR = pick(a.hist, par);
-    const int32_t *sR = pick(a.size, par);
-    int32_t *hW = pick(a.hist, par ^ 1);
-    int32_t *sW = pick(a.size, par ^ 1);
+    const int64_t khs = (int64_t)d.K * d.hs;
+    const int32_t *hR = pick(a.state, par);
+    const int32_t *sR = hR + khs;
+    int32_t *W = pick(a.state, par ^ 1);
     const bool exact = d.rule == SEEDS_BLOCK_EXACT;
     uint8_t *mine = sbin + seg * NPX;
+    (void)mine;
     for (int r = 0; r < rounds; ++r) {
         const int unit = (r * gridDim.x + blockIdx.x) * SEGS + seg;
         const bool in_range = unit < nunits;
@@ -138,18 +259,50 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                 nb = neighbourhood(units, uw, uh, ux, uy);
             }
         }
+        // The block's bins, whether or not the block turns out movable. Blocks of
+        // up to 64 pixels keep one bin per lane and group them with ballots;
+        // larger blocks are staged in LDS.
+        int j1 = 0xFF, cnt1 = 0;
+        bool first1 = false;
+        if constexpr (PPL == 1) {
+            const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
+            j1 = (in_range && x < d.W && y < d.H) ? a.bins[(int64_t)y * d.W + x] : 0xFF;
+            ballot_bins<SEG>(j1, cnt1, first1);
+        } else {
 #pragma unroll 4
-        for (int t = 0; t < PPL; ++t) {
-            const int q = lane + t * SEG;
-            const int x = ux * s + (q & (s - 1)), y = uy * s + (q >> level);
-            mine[q] = (nb.movable && x < d.W && y < d.H) ? a.bins[(int64_t)y * d.W + x] : 0xFF;
+            for (int tt = 0; tt < PPL; ++tt) {
+                const int q = lane + tt * SEG;
+                const int x = ux * s + (q & (s - 1)), y = uy * s + (q >> level);
+                mine[q] = (in_range && x < d.W && y < d.H) ? a.bins[(int64_t)y * d.W + x] : 0xFF;
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        // pixel tt of this lane: its bin j and, if it is the first of its bin in
+        // the block, the bin's count (0 otherwise)
+        auto leader_bin = [&](int tt, int &j, int &cnt) {
+            if constexpr (PPL == 1) {
+                j = j1;
+                cnt = first1 ? cnt1 : 0;
+            } else {
+                const int q = lane + tt * SEG;
+                j = mine[q];
+                cnt = 0;
+                if (j == 0xFF) return;
+                bool first = true;
+                for (int q2 = 0; q2 < NPX; ++q2) {
+                    const bool same = mine[q2] == j;
+                    cnt += same;
+                    first &= !(same && q2 < q);
+                }
+                if (!first) cnt = 0;
+            }
+        };
         if (nb.movable) {
             const int k = nb.k;
             const int64_t m = (int64_t)min(s, d.W - ux * s) * min(s, d.H - uy * s);
             if (pass != 2) {
-                // evaluate the candidates
+                // evaluate the candidates: every pixel that is the first of its
+                // bin in the block contributes for its bin j with count h_l(j)
                 const int64_t Ak = sR[k];
                 int64_t An[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -157,18 +310,10 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                     if (c < nb.nc) An[c] = sR[nb.cand[c]];
                 int64_t acc[4] = {0, 0, 0, 0}, acc_kl = 0;
 #pragma unroll 4
-                for (int t = 0; t < PPL; ++t) {
-                    const int q = lane + t * SEG;
-                    const int j = mine[q];
-                    if (j == 0xFF) continue;
-                    int cnt = 0;
-                    bool first = true;
-                    for (int q2 = 0; q2 < NPX; ++q2) {
-                        const bool same = mine[q2] == j;
-                        cnt += same;
-                        first &= !(same && q2 < q);
-                    }
-                    if (!first) continue;
+                for (int tt = 0; tt < PPL; ++tt) {
+                    int j, cnt;
+                    leader_bin(tt, j, cnt);
+                    if (!cnt) continue;
                     const int64_t hl = cnt;
                     const int64_t hk = hR[(int64_t)k * d.hs + j];
 #pragma unroll
@@ -176,21 +321,33 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                         if (c >= nb.nc) break;
                         const int64_t hn = hR[(int64_t)nb.cand[c] * d.hs + j];
                         if (exact) {
+                            // EXACT: h_l(j) (h_n(j) - h_k(j) + h_l(j))
                             acc[c] += hl * (hn - hk + hl);
                         } else {
+                            // Prop. 1: min(h_n(j) m, h_l(j) A_n)
                             const int64_t x1 = hn * m, x2 = hl * An[c];
                             acc[c] += x1 < x2 ? x1 : x2;
                         }
                     }
                     if (!exact) {
+                        // Prop. 1, k without the block: min((h_k - h_l) m, h_l (A_k - m))
                         const int64_t x1 = (hk - hl) * m, x2 = hl * (Ak - m);
                         acc_kl += x1 < x2 ? x1 : x2;
                     }
                 }
+                if constexpr (PPL == 1) {
+                    // at most 64 pixels and fewer than 2^23 in the image: every
+                    // term and sum is below 2^29 and fits 32 bits
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = segment_sum<SEG>(acc[c]);
-                acc_kl = segment_sum<SEG>(acc_kl);
-                // every lane holds the sums: every lane takes the same decision
+                    for (int c = 0; c < 4; ++c) acc[c] = segment_sum32<SEG>((int32_t)acc[c]);
+                    acc_kl = segment_sum32<SEG>((int32_t)acc_kl);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = segment_sum<SEG>(acc[c]);
+                    acc_kl = segment_sum<SEG>(acc_kl);
+                }
+                // every lane holds the sums: every lane takes the same decision;
+                // candidates are ascending, so ">" keeps the smaller label on ties
                 int64_t bS = acc[0], bA = An[0];
                 int bn = nb.cand[0];
 #pragma unroll
@@ -216,29 +373,25 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                 }
             }
             if (target >= 0) {
-                // apply: move the block's pixels bin by bin
-                if (lane == 0) units[(int64_t)uy * uw + ux] = target;
+                // apply (Sec. 5.3.3): the block's counts leave k and join target
+                if (lane == 0) {
+                    units[(int64_t)uy * uw + ux] = target;
+                    table_add(a, t, W, mylog, (int32_t)(khs + target), (int32_t)m);
+                    table_add(a, t, W, mylog, (int32_t)(khs + k), -(int32_t)m);
+                }
 #pragma unroll 4
-                for (int t = 0; t < PPL; ++t) {
-                    const int q = lane + t * SEG;
-                    const int j = mine[q];
-                    if (j == 0xFF) continue;
-                    int cnt = 0;
-                    bool first = true;
-                    for (int q2 = 0; q2 < NPX; ++q2) {
-                        const bool same = mine[q2] == j;
-                        cnt += same;
-                        first &= !(same && q2 < q);
-                    }
-                    if (!first) continue;
-                    move_counts(hW, sW, d.hs, k, target, j, cnt);
-                    log_move(a, mylog, s_logn, k, target, j, cnt);
+                for (int tt = 0; tt < PPL; ++tt) {
+                    int j, cnt;
+                    leader_bin(tt, j, cnt);
+                    if (!cnt) continue;
+                    table_add(a, t, W, mylog, target * d.hs + j, cnt);
+                    table_add(a, t, W, mylog, k * d.hs + j, -cnt);
                 }
             }
         } else if (in_range && pass == 1 && lane == 0) {
             a.pend[unit] = -1;
         }
-        __syncthreads();
+        if constexpr (PPL > 1) __syncthreads();  // LDS staging is reused next round
     }
 }
 
@@ -246,25 +399,28 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
 // registers and no scratch for the common hierarchies.
 template <bool BIG>
 __device__ inline void block_phase_any(const RefineArgs &a, int level, int cls, int par, int pass,
-                                uint32_t stamp, int32_t *units, uint8_t *sbin, int4 *mylog,
-                                int *s_logn) {
+                                       uint32_t stamp, int32_t *units, uint8_t *sbin,
+                                       DeltaTable &t, int2 *mylog) {
+#define SEEDS_BLOCK(SEG, PPL) \
+    block_phase<SEG, PPL>(a, level, cls, par, pass, stamp, units, sbin, t, mylog)
     if (!BIG) {
         switch (level) {
-            case 1: block_phase<4, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-            case 2: block_phase<16, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-            default: block_phase<64, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
+            case 1: SEEDS_BLOCK(4, 1); break;
+            case 2: SEEDS_BLOCK(16, 1); break;
+            default: SEEDS_BLOCK(64, 1); break;
         }
         return;
     }
     switch (level) {
-        case 1: block_phase<4, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        case 2: block_phase<16, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        case 3: block_phase<64, 1>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        case 4: block_phase<64, 4>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        case 5: block_phase<64, 16>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        case 6: block_phase<64, 64>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
-        default: block_phase<64, 256>(a, level, cls, par, pass, stamp, units, sbin, mylog, s_logn); break;
+        case 1: SEEDS_BLOCK(4, 1); break;
+        case 2: SEEDS_BLOCK(16, 1); break;
+        case 3: SEEDS_BLOCK(64, 1); break;
+        case 4: SEEDS_BLOCK(64, 4); break;
+        case 5: SEEDS_BLOCK(64, 16); break;
+        case 6: SEEDS_BLOCK(64, 64); break;
+        default: SEEDS_BLOCK(64, 256); break;
     }
+#undef SEEDS_BLOCK
 }
 
 // Level transition: every block of `level` splits into its 2x2 children.
@@ -281,5 +437,13 @@ __device__ inline void descend(const RefineArgs &a, int level, int cur_bl) {
     }
 }
 
+// Upper bound on the log entries (deltas) one workgroup produces in one round
+// of a phase at `level`.
+__host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
+    if (level == 0) return 2 * kPT;
+    const int segs = kPT / seg_lanes(level);
+    const int bins = min(1 << (2 * level), d.nb);
+    return segs * (2 * bins + 2);
+}
 
 }  // namespace seeds

@@ -12,23 +12,54 @@ template <bool BIG>
 __global__ __launch_bounds__(kPT) void k_phase(RefineArgs a, int level, int cls, int par, int pass,
                                                uint32_t stamp, int cur_bl, int replay_groups) {
     extern __shared__ uint8_t sbin[];
-    __shared__ int s_n;
-    if (threadIdx.x == 0) s_n = 0;
-    int32_t *hW = pick(a.hist, par ^ 1);
-    int32_t *sW = pick(a.size, par ^ 1);
-    for (int g = blockIdx.x; g < replay_groups; g += gridDim.x) {
+    __shared__ DeltaTable t;
+    __shared__ PixelList pl;
+    table_clear(t);
+    __syncthreads();
+    // The previous phase's deltas go to the copy this phase writes and nobody
+    // reads, as this phase's own deltas do; additions commute, so they need no
+    // ordering with the decisions. The log of slot blockIdx.x is fetched now,
+    // together with its length, and added at the end.
+    int32_t *W = pick(a.state, par ^ 1);
+    constexpr int kPre = 4;
+    int2 pre[kPre];
+    int pre_n = 0;
+    const bool replay_own = (int)blockIdx.x < replay_groups;
+    if (replay_own) {
+        const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + blockIdx.x;
+        const int2 *src_log = a.log + slot * a.log_cap;
+        pre_n = a.log_n[slot];
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * kPT;
+            pre[i] = e < a.log_cap ? src_log[e] : make_int2(0, 0);
+        }
+    }
+    int2 *mylog = a.log + ((int64_t)par * a.log_groups + blockIdx.x) * a.log_cap;
+    if (level == 0)
+        pixel_phase(a, cls, par, t, mylog, pl);
+    else
+        block_phase_any<BIG>(a, level, cls, par, pass, stamp, pick(a.bl, cur_bl), sbin, t, mylog);
+    if (replay_own) {
+        const int n = min(pre_n, a.log_cap);
+        const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + blockIdx.x;
+        const int2 *src_log = a.log + slot * a.log_cap;
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * kPT;
+            if (e < n) atomicAdd(&W[pre[i].x], pre[i].y);
+        }
+        replay(src_log + kPre * kPT, n - kPre * kPT, W);  // longer logs (large blocks)
+    }
+    for (int g = blockIdx.x + gridDim.x; g < replay_groups; g += gridDim.x) {
         const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + g;
-        replay(a, a.log + slot * a.log_cap, min(a.log_n[slot], a.log_cap), hW, sW);
+        replay(a.log + slot * a.log_cap, min(a.log_n[slot], a.log_cap), W);
     }
     __syncthreads();
-    int4 *mylog = a.log + ((int64_t)par * a.log_groups + blockIdx.x) * a.log_cap;
-    if (level == 0)
-        pixel_phase(a, cls, par, mylog, &s_n);
-    else
-        block_phase_any<BIG>(a, level, cls, par, pass, stamp, pick(a.bl, cur_bl), sbin, mylog,
-                             &s_n);
+    if (pass == 1) return;
+    table_flush(a, t, W, mylog);
     __syncthreads();
-    if (threadIdx.x == 0 && pass != 1) a.log_n[(int64_t)par * a.log_groups + blockIdx.x] = s_n;
+    if (threadIdx.x == 0) a.log_n[(int64_t)par * a.log_groups + blockIdx.x] = min(t.n, a.log_cap);
 }
 
 // After the last phase: add its deltas to the copy it read, so that both
@@ -36,9 +67,19 @@ __global__ __launch_bounds__(kPT) void k_phase(RefineArgs a, int level, int cls,
 __global__ __launch_bounds__(kPT) void k_replay(RefineArgs a, int par, int groups) {
     for (int g = blockIdx.x; g < groups; g += gridDim.x) {
         const int64_t slot = (int64_t)par * a.log_groups + g;
-        replay(a, a.log + slot * a.log_cap, min(a.log_n[slot], a.log_cap), pick(a.hist, par),
-               pick(a.size, par));
+        replay(a.log + slot * a.log_cap, min(a.log_n[slot], a.log_cap), pick(a.state, par));
     }
+}
+
+// Sizes from the histograms (pixel phases do not maintain them).
+__global__ __launch_bounds__(kPT) void k_sizes(Dims d, int32_t *state0, int32_t *state1) {
+    const int k = blockIdx.x * kPT + threadIdx.x;
+    if (k >= d.K) return;
+    int32_t sum = 0;
+    for (int j = 0; j < d.nb; ++j) sum += state0[(int64_t)k * d.hs + j];
+    const int64_t khs = (int64_t)d.K * d.hs;
+    state0[khs + k] = sum;
+    state1[khs + k] = sum;
 }
 
 }  // namespace
@@ -53,11 +94,16 @@ void phase_log_shape(const Dims &d, int *groups, int *cap) {
     int g = 1, c = 1;
     for (int l = 0; l < d.L; ++l) {
         g = max(g, phase_groups(d, l, 0));
-        const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
-        c = max(c, per_group * (l == 0 ? 1 : min(1 << (2 * l), d.nb)));
+        c = max(c, deltas_per_round(d, l));
     }
     *groups = g;
     *cap = c;
+}
+
+hipError_t launch_sizes(const Dims &d, const Buffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_sizes, dim3((d.K + kPT - 1) / kPT), dim3(kPT), 0, s, d, b.hist[0],
+                       b.hist[1]);
+    return hipGetLastError();
 }
 
 hipError_t launch_phase_kernel(const Dims &d, const Buffers &b, int log_groups, int log_cap,
@@ -69,10 +115,8 @@ hipError_t launch_phase_kernel(const Dims &d, const Buffers &b, int log_groups, 
     a.lab = b.lab;
     a.bl[0] = b.bl[0];
     a.bl[1] = b.bl[1];
-    a.hist[0] = b.hist[0];
-    a.hist[1] = b.hist[1];
-    a.size[0] = b.size[0];
-    a.size[1] = b.size[1];
+    a.state[0] = b.hist[0];
+    a.state[1] = b.hist[1];
     a.src = b.src;
     a.pend = b.pend;
     a.log = b.log;
