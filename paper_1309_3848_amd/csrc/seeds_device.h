@@ -81,6 +81,21 @@ __device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict
     return neighbourhood9(k, lN, lNE, lE, lSE, lS, lSW, lW, lNW);
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup b runs
+// on XCD b mod 8), each with its own L2. Renumbering them so that every XCD
+// gets a contiguous run of work keeps each XCD on one band of the image, so
+// its L2 fetches that band's labels and only the histograms of the
+// superpixels there. The renumbering is a bijection; results do not depend
+// on it.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_group() {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * q + min(x, r) + i;
+}
+
 // Segment-wide sum over SEG consecutive lanes of a wavefront (SEG <= 64).
 template <int SEG>
 __device__ __forceinline__ int64_t segment_sum(int64_t v) {

@@ -45,7 +45,8 @@ __global__ __launch_bounds__(kThreads) void k_init(Dims d, const uint8_t *__rest
     __shared__ int32_t sh_size[kMaxSlots];
     const int bw = (d.W + d.T - 1) / d.T, bh = (d.H + d.T - 1) / d.T;
     const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
-    const int x0 = (int)(blockIdx.x % tiles_x) * kInitTW, y0 = (int)(blockIdx.x / tiles_x) * kInitTH;
+    const int tile = xcd_group();
+    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * kInitTH;
     const int x1 = min(x0 + kInitTW, d.W) - 1, y1 = min(y0 + kInitTH, d.H) - 1;
     const int sx_lo = grid_col(x0, d, bw), sx_hi = grid_col(x1, d, bw);
     const int sy_lo = grid_row(y0, d, bh), sy_hi = grid_row(y1, d, bh);
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_init(Dims d, const uint8_t *__rest
 // or expand a block grid of a level into pixel labels.
 __global__ __launch_bounds__(kThreads) void k_upsample(const int32_t *__restrict__ from, int fw,
                                                        int32_t *__restrict__ to, int tw, int th) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_group() * blockDim.x + threadIdx.x;
     if (i >= (int64_t)tw * th) return;
     const int x = (int)(i % tw), y = (int)(i / tw);
     to[i] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_upsample(const int32_t *__restrict
 __global__ __launch_bounds__(kThreads) void k_expand(const int32_t *__restrict__ blab, int uw,
                                                      int level, int W, int H,
                                                      int32_t *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_group() * blockDim.x + threadIdx.x;
     if (i >= (int64_t)W * H) return;
     const int x = (int)(i % W), y = (int)(i / W);
     out[i] = blab[(int64_t)(y >> level) * uw + (x >> level)];

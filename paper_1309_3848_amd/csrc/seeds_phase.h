@@ -148,10 +148,11 @@ __device__ inline void pixel_phase(const RefineArgs &a, int cls, int par, DeltaT
     int32_t *W = pick(a.state, par ^ 1);
     const int per_round = gridDim.x * kPT;
     const int rounds = (n + per_round - 1) / per_round;
+    const int grp = xcd_group();
     for (int r = 0; r < rounds; ++r) {
         if (threadIdx.x == 0) pl.n = 0;
         __syncthreads();
-        const int i = r * per_round + blockIdx.x * kPT + threadIdx.x;
+        const int i = r * per_round + grp * kPT + threadIdx.x;
         bool take = false;
         if (i < n) take = pixel_movable(d, a.lab, cls % 3 + 3 * (i % ncx), cls / 3 + 3 * (i / ncx));
         wave_append(pl, take, i);
@@ -238,8 +239,9 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
     const bool exact = d.rule == SEEDS_BLOCK_EXACT;
     uint8_t *mine = sbin + seg * NPX;
     (void)mine;
+    const int grp = xcd_group();
     for (int r = 0; r < rounds; ++r) {
-        const int unit = (r * gridDim.x + blockIdx.x) * SEGS + seg;
+        const int unit = (r * gridDim.x + grp) * SEGS + seg;
         const bool in_range = unit < nunits;
         int ux = 0, uy = 0;
         Neighbourhood nb;
@@ -431,7 +433,7 @@ __device__ inline void descend(const RefineArgs &a, int level, int cur_bl) {
     int32_t *to = level == 1 ? a.lab : pick(a.bl, cur_bl ^ 1);
     const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
     const int64_t n = (int64_t)tw * th;
-    for (int64_t i = (int64_t)blockIdx.x * kPT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPT) {
+    for (int64_t i = (int64_t)xcd_group() * kPT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPT) {
         const int x = (int)(i % tw), y = (int)(i / tw);
         to[i] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
     }

@@ -18,22 +18,18 @@ __global__ __launch_bounds__(kPT) void k_phase(RefineArgs a, int level, int cls,
     __syncthreads();
     // The previous phase's deltas go to the copy this phase writes and nobody
     // reads, as this phase's own deltas do; additions commute, so they need no
-    // ordering with the decisions. The log of slot blockIdx.x is fetched now,
-    // together with its length, and added at the end.
+    // ordering with the decisions. The first kPre entries of the log of slot
+    // blockIdx.x are fetched now, together with its length, and added at the
+    // end; a longer log (rare) is read once its length is known.
     int32_t *W = pick(a.state, par ^ 1);
-    constexpr int kPre = 4;
-    int2 pre[kPre];
+    constexpr int kPre = 64;
+    int2 pre = make_int2(0, 0);
     int pre_n = 0;
     const bool replay_own = (int)blockIdx.x < replay_groups;
+    const int64_t own_slot = (int64_t)(par ^ 1) * a.log_groups + blockIdx.x;
     if (replay_own) {
-        const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + blockIdx.x;
-        const int2 *src_log = a.log + slot * a.log_cap;
-        pre_n = a.log_n[slot];
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * kPT;
-            pre[i] = e < a.log_cap ? src_log[e] : make_int2(0, 0);
-        }
+        pre_n = a.log_n[own_slot];
+        if (threadIdx.x < kPre) pre = a.log[own_slot * a.log_cap + threadIdx.x];
     }
     int2 *mylog = a.log + ((int64_t)par * a.log_groups + blockIdx.x) * a.log_cap;
     if (level == 0)
@@ -42,14 +38,11 @@ __global__ __launch_bounds__(kPT) void k_phase(RefineArgs a, int level, int cls,
         block_phase_any<BIG>(a, level, cls, par, pass, stamp, pick(a.bl, cur_bl), sbin, t, mylog);
     if (replay_own) {
         const int n = min(pre_n, a.log_cap);
-        const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + blockIdx.x;
-        const int2 *src_log = a.log + slot * a.log_cap;
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * kPT;
-            if (e < n) atomicAdd(&W[pre[i].x], pre[i].y);
+        if ((int)threadIdx.x < min(n, kPre)) atomicAdd(&W[pre.x], pre.y);
+        if (n > kPre) {
+            const int2 *src_log = a.log + own_slot * a.log_cap + kPre;
+            for (int e = threadIdx.x; e < n - kPre; e += kPT) atomicAdd(&W[src_log[e].x], src_log[e].y);
         }
-        replay(src_log + kPre * kPT, n - kPre * kPT, W);  // longer logs (large blocks)
     }
     for (int g = blockIdx.x + gridDim.x; g < replay_groups; g += gridDim.x) {
         const int64_t slot = (int64_t)(par ^ 1) * a.log_groups + g;
