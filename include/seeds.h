@@ -103,8 +103,9 @@ seeds_status seeds_init(seeds_ctx **out, const uint8_t *rgb, int32_t H, int32_t 
                         int64_t row_pitch_bytes, int32_t num_superpixels,
                         const seeds_params *p, void *hip_stream);
 
-/* Re-initialise an existing context from a new image of the same size and
- * parameters (no allocation): quantise, grid, histograms, schedule reset.     */
+/* Re-initialise an existing single-image context from a new image of the same
+ * size and parameters (no allocation): quantise, grid, histograms, schedule
+ * reset. A batch context takes seeds_batch_reinit.                            */
 seeds_status seeds_reinit(seeds_ctx *ctx, const uint8_t *rgb, int64_t row_pitch_bytes,
                           void *hip_stream);
 
@@ -147,8 +148,9 @@ typedef enum {
                                     grid-wide barriers between phases             */
 } seeds_launch_mode;
 
-/* Choose how later refine calls are launched. Results are identical in both
- * modes; the mode only changes the launch structure.                         */
+/* Choose how later refine calls are launched. Results are identical in all
+ * modes; the mode only changes the launch structure. SEEDS_LAUNCH_PERSISTENT
+ * is for single-image contexts (SEEDS_E_INVAL on a batch).                   */
 seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
 
 /* Wait for the stream and report device-side failures of earlier refine
@@ -156,6 +158,59 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  * SEEDS_E_DEVICE. seeds_labels and seeds_histograms with host outputs do the
  * same check.                                                                */
 seeds_status seeds_sync(seeds_ctx *ctx, void *hip_stream);
+
+/* ---- Batches ------------------------------------------------------------
+ * A batch context refines several independent images together: each image
+ * gets exactly the labels, histograms and sizes that a single-image context
+ * would give it (the method treats every image on its own, Sec. 5), and one
+ * launch per phase serves all of them. Images may differ in size, K and
+ * levels; bins, sweeps, gamma and the block rule are shared. The schedules
+ * are aligned at their end: with Lmax the most levels of any image, the
+ * batch walks the levels Lmax-1 .. 0 and an image of L levels takes part from
+ * level L-1 down. seeds_refine, seeds_refine_phases, seeds_set_launch_mode
+ * (graph and steps modes) and seeds_sync work on batches as on single images;
+ * seeds_level reports the batch's level (an image with fewer levels is at
+ * min(that, levels - 1)). The single-image calls seeds_labels,
+ * seeds_histograms and seeds_num_superpixels refer to image 0.              */
+#define SEEDS_MAX_BATCH 4096
+
+typedef struct {
+    const uint8_t *rgb;      /* device pointer, as for seeds_init                    */
+    int32_t height, width;   /* H, W                                                 */
+    int64_t row_pitch_bytes; /* >= 3 W                                               */
+    int32_t num_superpixels; /* requested K                                          */
+    int32_t levels;          /* L of this image, in [1,8]                            */
+} seeds_image;
+
+/* Create a batch context for count (1 .. SEEDS_MAX_BATCH) images and
+ * initialise every image (Sec. 5.1). p supplies bins, sweeps, gamma and the
+ * block rule (p->levels is ignored: each image has its own). Each image must
+ * satisfy the limits of seeds_init, and the state of the whole batch must
+ * stay below 2^31 cells: per image K_eff (hs + 1) rounded up to a multiple of
+ * 64, where hs is B^3 rounded up to a multiple of 8. An image that fails a
+ * check names its index in the error text. The call waits for the stream
+ * once (the batch tables are uploaded).                                      */
+seeds_status seeds_batch_init(seeds_ctx **out, const seeds_image *images, int32_t count,
+                              const seeds_params *p, void *hip_stream);
+
+/* Re-initialise every image of the context from new pixels of the same sizes:
+ * rgb[i] and row_pitch_bytes[i] (host arrays of seeds_batch_count entries).
+ * When a pointer or pitch differs from the previous call the call waits for
+ * the stream before uploading the new table; with unchanged pointers it
+ * enqueues only.                                                             */
+seeds_status seeds_batch_reinit(seeds_ctx *ctx, const uint8_t *const *rgb,
+                                const int64_t *row_pitch_bytes, void *hip_stream);
+
+/* Number of images of the context (1 for seeds_init contexts; -1 for NULL). */
+int32_t seeds_batch_count(const seeds_ctx *ctx);
+
+/* seeds_labels, seeds_histograms and seeds_num_superpixels for image `image`
+ * of the context (SEEDS_E_INVAL, or -1, when the index is out of range).    */
+seeds_status seeds_batch_labels(const seeds_ctx *ctx, int32_t image, int32_t *out,
+                                int32_t out_is_host, void *hip_stream);
+seeds_status seeds_batch_histograms(const seeds_ctx *ctx, int32_t image, int32_t *hist,
+                                    int32_t *size, int32_t out_is_host, void *hip_stream);
+int32_t seeds_batch_num_superpixels(const seeds_ctx *ctx, int32_t image);
 
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */

@@ -1,5 +1,11 @@
 // Internal declarations shared by the host side (seeds_capi.cpp) and the
-// kernels (seeds_kernels.hip) of libseeds.
+// kernels of libseeds.
+//
+// Every context is a batch of one or more images. Their buffers live in
+// pooled arenas; an ImageDesc gives each image's dimensions and offsets. One
+// phase launch processes the same phase (level, class) of every image that
+// takes part at that step of the schedule; a device array per launch maps
+// each workgroup to its image and its rank among that image's workgroups.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,7 +16,7 @@
 namespace seeds {
 
 // Histogram rows are padded so every row starts on a 32-byte boundary.
-inline int hist_stride(int nbins) { return (nbins + 7) & ~7; }
+__host__ __device__ inline int hist_stride(int nbins) { return (nbins + 7) & ~7; }
 
 struct Dims {
     int H, W;        // image
@@ -28,6 +34,9 @@ __host__ __device__ inline int units_h(const Dims &d, int level) { return (d.H +
 // Number of units of class c (3 (uy mod 3) + (ux mod 3)) on a uw x uh grid.
 __host__ __device__ inline int class_cols(int uw, int cls) { return cls % 3 < uw ? (uw - cls % 3 + 2) / 3 : 0; }
 __host__ __device__ inline int class_rows(int uh, int cls) { return cls / 3 < uh ? (uh - cls / 3 + 2) / 3 : 0; }
+__host__ __device__ inline int class_units(const Dims &d, int level, int cls) {
+    return class_cols(units_w(d, level), cls) * class_rows(units_h(d, level), cls);
+}
 
 // Schedule (Sec. 5.2): levels L-1 .. 0, I sweeps per level, nine classes
 // per sweep. `level` is the level whose unit grid currently holds the labels;
@@ -70,26 +79,38 @@ __host__ __device__ inline void sched_done(Sched &s, SchedOp op) {
     }
 }
 
-struct Buffers {
-    uint8_t *bins;     // H*W colour bin of every pixel
-    int32_t *lab;      // H*W pixel labels (valid at level 0)
-    int32_t *bl[2];    // block-label grids, ping-pong (levels >= 1)
-    int32_t *hist[2];  // state copy c: K*hs colour-histogram cells in pixel counts,
-                       // immediately followed by the K superpixel sizes; the two
-                       // copies are equal between launches and alternate in phases
-    int32_t *size[2];  // = hist[c] + K*hs
-    int32_t *src;      // K phase stamps of move sources (exact rule's drop rule)
-    int32_t *pend;     // one decision per class unit: target label or -1
-    int2 *log;         // per-workgroup delta logs, 2 parities x groups x cap (index, delta)
-    int32_t *log_n;    // per-phase launches: entries in each log, 2 x groups
-    uint32_t *sync;    // persistent kernel: barrier count, generation, error flag
+// One image of a context: its dimensions and its offsets into the arenas.
+// The block grid of level l >= 1 lives in block-grid buffer l % 2.
+struct ImageDesc {
+    Dims d;
+    int64_t bins;      // byte offset into the bins arena (H * W)
+    int64_t lab;       // element offset into the label arena (H * W)
+    int64_t bl[2];     // element offsets into the block-grid arena
+    int64_t state;     // element offset into each state copy: K * hs cells, then K sizes
+    int64_t src;       // element offset into the source-stamp arena (K)
+    int64_t pend;      // element offset into the decision arena (largest class)
 };
 
-// Persistent-kernel launch geometry, fixed per context.
-struct PersistentGeom {
-    int groups;     // co-resident workgroups
-    int log_cap;    // log entries per workgroup and phase parity
-    int lds_bytes;  // dynamic LDS for staging block bins
+// Arenas of a context.
+struct Arenas {
+    uint8_t *bins;
+    int32_t *lab;
+    int32_t *bl;
+    int32_t *state[2];  // two equal copies between launches; phases alternate them
+    int32_t *src;       // phase stamps of move sources (exact rule's drop rule)
+    int32_t *pend;      // exact rule: one decision per class unit
+    int2 *log;          // per-workgroup delta logs: [2 parities][log_groups][log_cap]
+    int32_t *log_n;     // entries in each log: [2][log_groups]
+    uint32_t *sync;     // persistent kernel: barrier count, generation, error flag
+};
+
+// Device view of a whole context for one launch.
+struct BatchArgs {
+    const ImageDesc *imgs;  // device array, nimg entries
+    int nimg;
+    Arenas ar;
+    int log_cap;
+    int log_groups;
 };
 
 constexpr int kPersistentThreads = 256;
@@ -99,27 +120,73 @@ constexpr int kPersistentThreads = 256;
 __host__ __device__ inline int seg_lanes(int level) { return level >= 3 ? 64 : 1 << (2 * level); }
 __host__ __device__ inline int seg_ppl(int level) { return level >= 3 ? 1 << (2 * level - 6) : 1; }
 
-// Launchers (seeds_kernels.hip). They only enqueue work and return the launch
-// status; shapes are checked by the caller.
+// Units one workgroup of a phase launch handles at `level`, and workgroups an
+// image needs for one phase of class cls.
+__host__ __device__ inline int units_per_group(int level) {
+    return level == 0 ? kPersistentThreads : kPersistentThreads / seg_lanes(level);
+}
+__host__ __device__ inline int phase_groups(const Dims &d, int level, int cls) {
+    const int per = units_per_group(level);
+    return (class_units(d, level, cls) + per - 1) / per;
+}
+
+// Upper bound on the log entries (deltas) one workgroup produces in one round
+// of a phase at `level`.
+__host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
+    if (level == 0) return 2 * kPersistentThreads;
+    const int segs = kPersistentThreads / seg_lanes(level);
+    const int bins = (1 << (2 * level)) < d.nb ? (1 << (2 * level)) : d.nb;
+    return segs * (2 * bins + 2);
+}
+
+// Workgroups of one descend launch for an image and of one init launch.
+__host__ __device__ inline int descend_groups(const Dims &d, int level) {
+    const int64_t n = (int64_t)units_w(d, level - 1) * units_h(d, level - 1);
+    return (int)((n + kPersistentThreads - 1) / kPersistentThreads);
+}
+constexpr int kInitTW = 64, kInitTH = 16;
+__host__ __device__ inline int init_groups(const Dims &d) {
+    return ((d.W + kInitTW - 1) / kInitTW) * ((d.H + kInitTH - 1) / kInitTH);
+}
+
+// Persistent-kernel launch geometry, fixed per single-image context.
+struct PersistentGeom {
+    int groups;     // co-resident workgroups
+    int log_cap;    // log entries per workgroup and phase parity
+    int lds_bytes;  // dynamic LDS for staging block bins
+};
+
+// Launchers. They only enqueue work and return the launch status; shapes are
+// checked by the caller. For a single image (b.nimg == 1) the launch uses
+// `one` and needs no map; for a batch, map[logical workgroup] = (image, rank
+// of the workgroup among that image's workgroups of the launch) and `groups`
+// is the launch's total.
 hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-hipError_t launch_init(const Dims &d, const Buffers &b, const uint8_t *rgb, int64_t pitch,
-                       int32_t *top_labels, hipStream_t s);
-// One phase as one launch (level >= 0), or the final replay of the last
-// phase's logs into the copy it read (level < 0). pass: 0 decide and apply,
-// 1 exact-rule decide only, 2 exact-rule apply.
-hipError_t launch_phase_kernel(const Dims &d, const Buffers &b, int log_groups, int log_cap,
-                               int level, int cls, int par, int pass, uint32_t stamp, int cur_bl,
-                               int replay_groups, hipStream_t s);
-int phase_groups(const Dims &d, int level, int cls);
-hipError_t launch_sizes(const Dims &d, const Buffers &b, hipStream_t s);
-void phase_log_shape(const Dims &d, int *groups, int *cap);
-hipError_t launch_refine(const Dims &d, const Buffers &b, const PersistentGeom &g,
-                         const Sched &start, int cur_bl, int max_phases, uint32_t stamp,
+hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
+                       int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
+                       const int64_t *pitch_table, int groups, hipStream_t s);
+// One phase as one launch. pass: 0 decide and apply, 1 exact-rule decide
+// only, 2 exact-rule apply. replay_groups: workgroups of the previous phase
+// launch, whose logs (parity par ^ 1) this launch adds to its write copy.
+// max_level: the largest level of any image (selects the kernel variant).
+hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
+                        int level, int cls, int par, int pass, uint32_t stamp, int groups,
+                        int replay_groups, hipStream_t s);
+// Add the logs of the last phase launch (parity par, `groups` slots) to the
+// copy that phase read.
+hipError_t launch_final_replay(const BatchArgs &b, int par, int groups, hipStream_t s);
+// Split every block of `level` into its 2x2 children (level 1: pixel labels).
+hipError_t launch_descend(const BatchArgs &b, const ImageDesc &one, const int2 *map, int level,
+                          int groups, hipStream_t s);
+// Sizes from the histograms of one image (pixel phases do not maintain them).
+hipError_t launch_sizes(const Dims &d, int32_t *state0, int32_t *state1, hipStream_t s);
+// Pixel labels of one image from the unit grid of `level`.
+hipError_t launch_expand(const Dims &d, const int32_t *units, int level, int32_t *out,
                          hipStream_t s);
+
+// Persistent cooperative refinement of a single image.
+hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,
+                         const Sched &start, int max_phases, uint32_t stamp, hipStream_t s);
 PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu);
-hipError_t launch_upsample(const int32_t *from, int fw, int fh, int32_t *to, int tw, int th,
-                           hipStream_t s);
-hipError_t launch_expand(const Dims &d, const int32_t *blab, int level, int32_t *out,
-                         hipStream_t s);
 
 }  // namespace seeds

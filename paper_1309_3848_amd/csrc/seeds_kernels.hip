@@ -24,7 +24,6 @@ __global__ void k_fill(int32_t *__restrict__ p, int32_t v, int64_t n) {
 // histograms are accumulated in LDS and merged into the global ones once
 // per (superpixel, bin). Tiles that meet more than kMaxSlots superpixels
 // (tiny superpixels) fall back to global atomics.
-constexpr int kInitTW = 64, kInitTH = 16;
 constexpr int kMaxSlots = 32, kMaxHs = 224;  // hs <= 224 for B <= 6
 
 __device__ __forceinline__ int grid_col(int x, const Dims &d, int bw) {
@@ -34,18 +33,19 @@ __device__ __forceinline__ int grid_row(int y, const Dims &d, int bh) {
     return (int)(((int64_t)(y / d.T) * d.gy) / bh);
 }
 
-__global__ __launch_bounds__(kThreads) void k_init(Dims d, const uint8_t *__restrict__ rgb,
-                                                   int64_t pitch, uint8_t *__restrict__ bins,
-                                                   int32_t *__restrict__ top,
-                                                   int32_t *__restrict__ hist,
-                                                   int32_t *__restrict__ size,
-                                                   int32_t *__restrict__ hist2,
-                                                   int32_t *__restrict__ size2) {
-    __shared__ int32_t sh_hist[kMaxSlots * kMaxHs];
-    __shared__ int32_t sh_size[kMaxSlots];
+struct InitSlots {
+    int32_t hist[kMaxSlots * kMaxHs];
+    int32_t size[kMaxSlots];
+};
+
+// One tile of one image. st0 / st1: the image's state in both copies.
+__device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
+                          uint8_t *__restrict__ bins, int32_t *__restrict__ top,
+                          int32_t *__restrict__ st0, int32_t *__restrict__ st1, int tile,
+                          InitSlots &sl) {
+    const int64_t khs = (int64_t)d.K * d.hs;
     const int bw = (d.W + d.T - 1) / d.T, bh = (d.H + d.T - 1) / d.T;
     const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
-    const int tile = xcd_group();
     const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * kInitTH;
     const int x1 = min(x0 + kInitTW, d.W) - 1, y1 = min(y0 + kInitTH, d.H) - 1;
     const int sx_lo = grid_col(x0, d, bw), sx_hi = grid_col(x1, d, bw);
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kThreads) void k_init(Dims d, const uint8_t *__rest
     const int nslots = nsx * (sy_hi - sy_lo + 1);
     const bool local = nslots <= kMaxSlots;
     if (local) {
-        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) sh_hist[i] = 0;
-        for (int i = threadIdx.x; i < nslots; i += kThreads) sh_size[i] = 0;
+        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) sl.hist[i] = 0;
+        for (int i = threadIdx.x; i < nslots; i += kThreads) sl.size[i] = 0;
     }
     __syncthreads();
     const int x = x0 + (int)(threadIdx.x % kInitTW);
@@ -70,45 +70,63 @@ __global__ __launch_bounds__(kThreads) void k_init(Dims d, const uint8_t *__rest
         if (x % d.T == 0 && y % d.T == 0) top[(int64_t)(y / d.T) * bw + x / d.T] = label;
         if (local) {
             const int slot = (sy - sy_lo) * nsx + (sx - sx_lo);
-            atomicAdd(&sh_hist[slot * d.hs + j], 1);
-            atomicAdd(&sh_size[slot], 1);
+            atomicAdd(&sl.hist[slot * d.hs + j], 1);
+            atomicAdd(&sl.size[slot], 1);
         } else {
-            atomicAdd(&hist[(int64_t)label * d.hs + j], 1);
-            atomicAdd(&size[label], 1);
-            atomicAdd(&hist2[(int64_t)label * d.hs + j], 1);
-            atomicAdd(&size2[label], 1);
+            atomicAdd(&st0[(int64_t)label * d.hs + j], 1);
+            atomicAdd(&st0[khs + label], 1);
+            atomicAdd(&st1[(int64_t)label * d.hs + j], 1);
+            atomicAdd(&st1[khs + label], 1);
         }
     }
     __syncthreads();
     if (!local) return;
     for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) {
-        const int v = sh_hist[i];
+        const int v = sl.hist[i];
         if (!v) continue;
         const int slot = i / d.hs, j = i - slot * d.hs;
         const int label = (sy_lo + slot / nsx) * d.gx + sx_lo + slot % nsx;
-        atomicAdd(&hist[(int64_t)label * d.hs + j], v);
-        atomicAdd(&hist2[(int64_t)label * d.hs + j], v);
+        atomicAdd(&st0[(int64_t)label * d.hs + j], v);
+        atomicAdd(&st1[(int64_t)label * d.hs + j], v);
     }
     for (int i = threadIdx.x; i < nslots; i += kThreads) {
-        const int v = sh_size[i];
+        const int v = sl.size[i];
         if (!v) continue;
-        atomicAdd(&size[(sy_lo + i / nsx) * d.gx + sx_lo + i % nsx], v);
-        atomicAdd(&size2[(sy_lo + i / nsx) * d.gx + sx_lo + i % nsx], v);
+        const int label = (sy_lo + i / nsx) * d.gx + sx_lo + i % nsx;
+        atomicAdd(&st0[khs + label], v);
+        atomicAdd(&st1[khs + label], v);
     }
 }
 
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// Level transitions: split every block into its 2x2 children (Sec. 5.1),
-// or expand a block grid of a level into pixel labels.
-__global__ __launch_bounds__(kThreads) void k_upsample(const int32_t *__restrict__ from, int fw,
-                                                       int32_t *__restrict__ to, int tw, int th) {
-    const int64_t i = (int64_t)xcd_group() * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)tw * th) return;
-    const int x = (int)(i % tw), y = (int)(i / tw);
-    to[i] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
+__device__ __forceinline__ void init_image(const BatchArgs &b, const ImageDesc &g,
+                                           const uint8_t *rgb, int64_t pitch, int tile,
+                                           InitSlots &sl) {
+    const Dims &d = g.d;
+    // the top blocks' grid (level L-1) lives in block-grid buffer (L-1) % 2;
+    // with one level the top blocks are the pixels
+    int32_t *top = d.L > 1 ? b.ar.bl + g.bl[(d.L - 1) & 1] : b.ar.lab + g.lab;
+    init_tile(d, rgb, pitch, b.ar.bins + g.bins, top, b.ar.state[0] + g.state,
+              b.ar.state[1] + g.state, tile, sl);
 }
 
+__global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
+                                                   const uint8_t *rgb_one, int64_t pitch_one,
+                                                   const int2 *map,
+                                                   const uint8_t *const *rgb_table,
+                                                   const int64_t *pitch_table) {
+    __shared__ InitSlots sl;
+    const int lg = xcd_group();
+    if (b.nimg == 1) {
+        init_image(b, one, rgb_one, pitch_one, lg, sl);
+        return;
+    }
+    const int2 e = map[lg];
+    init_image(b, b.imgs[e.x], rgb_table[e.x], pitch_table[e.x], e.y, sl);
+}
+
+// ---------------------------------------------------------------------------
+// Pixel labels of one image from a block grid of a level (output of a state
+// stopped at a block level).
 __global__ __launch_bounds__(kThreads) void k_expand(const int32_t *__restrict__ blab, int uw,
                                                      int level, int W, int H,
                                                      int32_t *__restrict__ out) {
@@ -129,23 +147,11 @@ hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Dims &d, const Buffers &b, const uint8_t *rgb, int64_t pitch,
-                       int32_t *top_labels, hipStream_t s) {
-    // the two state copies (histograms, then sizes) are contiguous
-    hipError_t e = launch_fill(b.hist[0], 0, 2 * ((int64_t)d.K * d.hs + d.K), s);
-    if (e != hipSuccess) return e;
-    const unsigned tiles = blocks_for(d.W, kInitTW) * blocks_for(d.H, kInitTH);
-    hipLaunchKernelGGL(k_init, dim3(tiles), dim3(kThreads), 0, s, d, rgb, pitch, b.bins, top_labels,
-                       b.hist[0], b.size[0], b.hist[1], b.size[1]);
-    return hipGetLastError();
-}
-
-hipError_t launch_upsample(const int32_t *from, int fw, int fh, int32_t *to, int tw, int th,
-                           hipStream_t s) {
-    (void)fh;
-    const int64_t n = (int64_t)tw * th;
-    hipLaunchKernelGGL(k_upsample, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, from, fw,
-                       to, tw, th);
+hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
+                       int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
+                       const int64_t *pitch_table, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one, map,
+                       rgb_table, pitch_table);
     return hipGetLastError();
 }
 

@@ -58,19 +58,29 @@ __device__ bool grid_sync(uint32_t *sync, uint32_t &gen) {
     return s_ok;
 }
 
+struct RefineLaunch {
+    BatchArgs b;  // a single image: b.nimg == 1
+    ImageDesc one;
+    Sched start;
+    int max_phases;
+    uint32_t stamp;  // stamp of the phase before the first one of the launch
+};
+
 template <bool BIG>
-__global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
+__global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
     __shared__ PixelList pl;
     __shared__ int s_prev_n;
-    const Dims &d = a.d;
-    uint32_t gen = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int2 *const log0 = a.log + (int64_t)blockIdx.x * a.log_cap;
-    int2 *const log1 = a.log + ((int64_t)gridDim.x + blockIdx.x) * a.log_cap;
+    const BatchArgs &b = a.b;
+    const Dims &d = a.one.d;
+    const ImageView v = make_view(b, a.one, xcd_group(), gridDim.x);
+    uint32_t *sync = b.ar.sync;
+    uint32_t gen = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int2 *const log0 = b.ar.log + (int64_t)blockIdx.x * b.log_cap;
+    int2 *const log1 = b.ar.log + ((int64_t)gridDim.x + blockIdx.x) * b.log_cap;
     if (threadIdx.x == 0) s_prev_n = 0;
     Sched sc = a.start;
-    int cur_bl = a.cur_bl;
     int par = 0;  // state copy holding the current state
     int phases = 0;
     uint32_t stamp = a.stamp;
@@ -79,43 +89,39 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineArgs a) {
         const SchedOp op = sched_next(d, sc, a.max_phases < 0 ? -1 : a.max_phases - phases, &cls);
         if (op == OP_END) break;
         if (op == OP_DESCEND) {
-            descend(a, sc.level, cur_bl);
-            if (sc.level > 1) cur_bl ^= 1;
-            if (!grid_sync(a.sync, gen)) return;
+            descend(v, sc.level);
+            if (!grid_sync(sync, gen)) return;
         } else {
-            int32_t *W = pick(a.state, par ^ 1);
+            int32_t *W = pick(b.ar.state, par ^ 1);
             int2 *cur_log = par ? log1 : log0;
             const int2 *prev_log = par ? log0 : log1;
             const int prev_n = s_prev_n;
             table_clear(t);
             __syncthreads();
             // the previous phase's deltas, logged by this workgroup
-            if (phases > 0) replay(prev_log, min(prev_n, a.log_cap), W);
+            if (phases > 0) replay(prev_log, min(prev_n, b.log_cap), W);
             ++stamp;
             if (sc.level == 0) {
-                pixel_phase(a, cls, par, t, cur_log, pl);
+                pixel_phase(b, v, cls, par, t, cur_log, pl);
+            } else if (d.rule == SEEDS_BLOCK_EXACT) {
+                block_phase_any<BIG>(b, v, sc.level, cls, par, 1, stamp, sbin, t, cur_log);
+                if (!grid_sync(sync, gen)) return;
+                block_phase_any<BIG>(b, v, sc.level, cls, par, 2, stamp, sbin, t, cur_log);
             } else {
-                int32_t *units = pick(a.bl, cur_bl);
-                if (d.rule == SEEDS_BLOCK_EXACT) {
-                    block_phase_any<BIG>(a, sc.level, cls, par, 1, stamp, units, sbin, t, cur_log);
-                    if (!grid_sync(a.sync, gen)) return;
-                    block_phase_any<BIG>(a, sc.level, cls, par, 2, stamp, units, sbin, t, cur_log);
-                } else {
-                    block_phase_any<BIG>(a, sc.level, cls, par, 0, stamp, units, sbin, t, cur_log);
-                }
+                block_phase_any<BIG>(b, v, sc.level, cls, par, 0, stamp, sbin, t, cur_log);
             }
             __syncthreads();
-            table_flush(a, t, W, cur_log);
+            table_flush(b, t, W, cur_log);
             __syncthreads();
             if (threadIdx.x == 0) s_prev_n = t.n;
-            if (!grid_sync(a.sync, gen)) return;
+            if (!grid_sync(sync, gen)) return;
             par ^= 1;
             ++phases;
         }
         sched_done(sc, op);
     }
     // the copy read by the last phase lacks that phase's deltas
-    if (phases > 0) replay(par ? log0 : log1, min(s_prev_n, a.log_cap), pick(a.state, par ^ 1));
+    if (phases > 0) replay(par ? log0 : log1, min(s_prev_n, b.log_cap), pick(b.ar.state, par ^ 1));
 }
 
 }  // namespace
@@ -154,30 +160,18 @@ PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu)
     return g;
 }
 
-hipError_t launch_refine(const Dims &d, const Buffers &b, const PersistentGeom &g,
-                         const Sched &start, int cur_bl, int max_phases, uint32_t stamp,
-                         hipStream_t s) {
-    RefineArgs a;
-    a.d = d;
-    a.bins = b.bins;
-    a.lab = b.lab;
-    a.bl[0] = b.bl[0];
-    a.bl[1] = b.bl[1];
-    a.state[0] = b.hist[0];
-    a.state[1] = b.hist[1];
-    a.src = b.src;
-    a.pend = b.pend;
-    a.log = b.log;
-    a.log_n = b.log_n;
-    a.log_cap = g.log_cap;
-    a.log_groups = g.groups;
-    a.sync = b.sync;
+hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,
+                         const Sched &start, int max_phases, uint32_t stamp, hipStream_t s) {
+    RefineLaunch a;
+    a.b = b;
+    a.b.log_cap = g.log_cap;
+    a.b.log_groups = g.groups;
+    a.one = one;
     a.start = start;
-    a.cur_bl = cur_bl;
     a.max_phases = max_phases;
     a.stamp = stamp;
     void *args[] = {&a};
-    const void *fn = d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    const void *fn = one.d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
     return hipLaunchCooperativeKernel(fn, dim3(g.groups), dim3(kPT), args, (unsigned)g.lds_bytes,
                                       s);
 }

@@ -18,6 +18,12 @@
 // it as (index, delta). Neighbouring moves mostly share cells, so this cuts
 // the global atomics and the log. Pixel phases leave the sizes alone: only
 // the Prop. 1 block rule reads them, and pixel phases come last.
+//
+// Batches. Each workgroup serves one image: ImageView holds that image's
+// dimensions, buffers and state, and the rank of the workgroup among the
+// image's workgroups of the launch. Log entries hold global state indices
+// (the image's state offset plus the local index), so any workgroup of the
+// next launch can add them.
 #pragma once
 
 #include "seeds_device.h"
@@ -26,24 +32,37 @@ namespace seeds {
 
 constexpr int kPT = kPersistentThreads;
 
-struct RefineArgs {
+struct ImageView {
     Dims d;
     const uint8_t *bins;
     int32_t *lab;
-    int32_t *bl[2];
-    int32_t *state[2];  // copy c: K * hs histogram cells, then K sizes
+    int32_t *bl0, *bl1;  // block grids of this image (level l in bl[l % 2])
+    int64_t base;        // global index of this image's state in a state copy
     int32_t *src;
     int32_t *pend;
-    int2 *log;          // move logs: [2 parities][log_groups][log_cap] (index, delta)
-    int32_t *log_n;     // per-phase launches: entries in each log, [2][log_groups]
-    int log_cap;
-    int log_groups;
-    uint32_t *sync;     // persistent kernel: [0] arrivals, [1] generation, [2] error flag
-    Sched start;
-    int cur_bl;
-    int max_phases;
-    uint32_t stamp;     // stamp of the phase before the first one of the launch
+    int grp;             // rank of this workgroup among the image's workgroups
+    int ngroups;         // the image's workgroups in this launch
 };
+
+__device__ __forceinline__ int32_t *level_grid(const ImageView &v, int level) {
+    return (level & 1) ? v.bl1 : v.bl0;
+}
+
+__device__ __forceinline__ ImageView make_view(const BatchArgs &b, const ImageDesc &g, int grp,
+                                               int ngroups) {
+    ImageView v;
+    v.d = g.d;
+    v.bins = b.ar.bins + g.bins;
+    v.lab = b.ar.lab + g.lab;
+    v.bl0 = b.ar.bl + g.bl[0];
+    v.bl1 = b.ar.bl + g.bl[1];
+    v.base = g.state;
+    v.src = b.ar.src + g.src;
+    v.pend = b.ar.pend + g.pend;
+    v.grp = grp;
+    v.ngroups = ngroups;
+    return v;
+}
 
 // Pointer selection by a run-time index without indexing an array (which would
 // put the array in scratch memory).
@@ -73,18 +92,18 @@ __device__ __forceinline__ void table_clear(DeltaTable &t) {
     if (threadIdx.x == 0) t.n = 0;
 }
 
-__device__ __forceinline__ void log_append(const RefineArgs &a, DeltaTable &t, int2 *mylog,
+__device__ __forceinline__ void log_append(const BatchArgs &b, DeltaTable &t, int2 *mylog,
                                            int32_t idx, int32_t delta) {
     const int slot = atomicAdd(&t.n, 1);
-    if (slot < a.log_cap)
+    if (slot < b.log_cap)
         mylog[slot] = make_int2(idx, delta);
     else
-        __hip_atomic_store(&a.sync[2], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&b.ar.sync[2], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Add delta to state index idx. A full neighbourhood in the table sends the
-// delta straight to the write copy and the log.
-__device__ __forceinline__ void table_add(const RefineArgs &a, DeltaTable &t, int32_t *W,
+// Add delta to global state index idx. A full neighbourhood in the table sends
+// the delta straight to the write copy W and the log.
+__device__ __forceinline__ void table_add(const BatchArgs &b, DeltaTable &t, int32_t *W,
                                           int2 *mylog, int32_t idx, int32_t delta) {
     uint32_t h = ((uint32_t)idx * 2654435761u) >> (32 - kTableBits);
 #pragma nounroll
@@ -96,18 +115,18 @@ __device__ __forceinline__ void table_add(const RefineArgs &a, DeltaTable &t, in
         }
     }
     atomicAdd(&W[idx], delta);
-    log_append(a, t, mylog, idx, delta);
+    log_append(b, t, mylog, idx, delta);
 }
 
 // After the phase's moves (and a workgroup barrier): one global atomic and one
 // log entry per non-zero sum.
-__device__ __forceinline__ void table_flush(const RefineArgs &a, DeltaTable &t, int32_t *W,
+__device__ __forceinline__ void table_flush(const BatchArgs &b, DeltaTable &t, int32_t *W,
                                             int2 *mylog) {
     for (int i = threadIdx.x; i < kTableSize; i += kPT) {
         const int32_t k = t.key[i], v = t.val[i];
         if (k == kEmptyKey || v == 0) continue;
         atomicAdd(&W[k], v);
-        log_append(a, t, mylog, k, v);
+        log_append(b, t, mylog, k, v);
     }
 }
 
@@ -139,32 +158,32 @@ __device__ __forceinline__ void wave_append(PixelList &pl, bool take, int value)
     if (take) pl.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
 }
 
-__device__ inline void pixel_phase(const RefineArgs &a, int cls, int par, DeltaTable &t,
-                                   int2 *mylog, PixelList &pl) {
-    const Dims &d = a.d;
+__device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int cls, int par,
+                                   DeltaTable &t, int2 *mylog, PixelList &pl) {
+    const Dims &d = v.d;
     const int ncx = class_cols(d.W, cls), ncy = class_rows(d.H, cls);
     const int n = ncx * ncy;
-    const int32_t *hR = pick(a.state, par);
-    int32_t *W = pick(a.state, par ^ 1);
-    const int per_round = gridDim.x * kPT;
+    const int32_t *hR = pick(b.ar.state, par) + v.base;
+    int32_t *W = pick(b.ar.state, par ^ 1);
+    const int per_round = v.ngroups * kPT;
     const int rounds = (n + per_round - 1) / per_round;
-    const int grp = xcd_group();
+    const int grp = v.grp;
     for (int r = 0; r < rounds; ++r) {
         if (threadIdx.x == 0) pl.n = 0;
         __syncthreads();
         const int i = r * per_round + grp * kPT + threadIdx.x;
         bool take = false;
-        if (i < n) take = pixel_movable(d, a.lab, cls % 3 + 3 * (i % ncx), cls / 3 + 3 * (i / ncx));
+        if (i < n) take = pixel_movable(d, v.lab, cls % 3 + 3 * (i % ncx), cls / 3 + 3 * (i / ncx));
         wave_append(pl, take, i);
         __syncthreads();
         if ((int)threadIdx.x < pl.n) {
             const int u = pl.unit[threadIdx.x];
             const int x = cls % 3 + 3 * (u % ncx), y = cls / 3 + 3 * (u / ncx);
-            const PixelMove mv = pixel_decision(d, a.lab, a.bins, hR, x, y);
+            const PixelMove mv = pixel_decision(d, v.lab, v.bins, hR, x, y);
             if (mv.n >= 0) {
-                a.lab[(int64_t)y * d.W + x] = mv.n;
-                table_add(a, t, W, mylog, mv.n * d.hs + mv.j, 1);
-                table_add(a, t, W, mylog, mv.k * d.hs + mv.j, -1);
+                v.lab[(int64_t)y * d.W + x] = mv.n;
+                table_add(b, t, W, mylog, (int32_t)(v.base + mv.n * d.hs + mv.j), 1);
+                table_add(b, t, W, mylog, (int32_t)(v.base + mv.k * d.hs + mv.j), -1);
             }
         }
         __syncthreads();
@@ -219,29 +238,30 @@ __device__ __forceinline__ void ballot_bins(int j, int &cnt, bool &first) {
 //   pass 1: exact rule, decide only: record the target and stamp the source
 //   pass 2: exact rule, apply the recorded moves whose target is no source
 template <int SEG, int PPL>
-__device__ inline void block_phase(const RefineArgs &a, int level, int cls, int par, int pass,
-                                   uint32_t stamp, int32_t *units, uint8_t *sbin, DeltaTable &t,
-                                   int2 *mylog) {
+__device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int level, int cls,
+                                   int par, int pass, uint32_t stamp, uint8_t *sbin,
+                                   DeltaTable &t, int2 *mylog) {
     constexpr int SEGS = kPT / SEG;
     constexpr int NPX = SEG * PPL;
-    const Dims &d = a.d;
+    const Dims &d = v.d;
+    int32_t *units = level_grid(v, level);
     const int s = 1 << level;
     const int uw = units_w(d, level), uh = units_h(d, level);
     const int ncx = class_cols(uw, cls), ncy = class_rows(uh, cls);
     const int nunits = ncx * ncy;
-    const int per_round = gridDim.x * SEGS;
+    const int per_round = v.ngroups * SEGS;
     const int rounds = (nunits + per_round - 1) / per_round;
     const int seg = threadIdx.x / SEG, lane = threadIdx.x % SEG;
     const int64_t khs = (int64_t)d.K * d.hs;
-    const int32_t *hR = pick(a.state, par);
+    const int32_t *hR = pick(b.ar.state, par) + v.base;
     const int32_t *sR = hR + khs;
-    int32_t *W = pick(a.state, par ^ 1);
+    int32_t *W = pick(b.ar.state, par ^ 1);
     const bool exact = d.rule == SEEDS_BLOCK_EXACT;
     uint8_t *mine = sbin + seg * NPX;
     (void)mine;
-    const int grp = xcd_group();
+    const int grp = v.grp;
     for (int r = 0; r < rounds; ++r) {
-        const int unit = (r * gridDim.x + grp) * SEGS + seg;
+        const int unit = (r * v.ngroups + grp) * SEGS + seg;
         const bool in_range = unit < nunits;
         int ux = 0, uy = 0;
         Neighbourhood nb;
@@ -253,8 +273,8 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
             ux = cls % 3 + 3 * (unit % ncx);
             uy = cls / 3 + 3 * (unit / ncx);
             if (pass == 2) {
-                target = a.pend[unit];
-                if (target >= 0 && a.src[target] == (int32_t)stamp) target = -1;
+                target = v.pend[unit];
+                if (target >= 0 && v.src[target] == (int32_t)stamp) target = -1;
                 nb.movable = target >= 0;
                 nb.k = units[(int64_t)uy * uw + ux];
             } else {
@@ -268,14 +288,14 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
         bool first1 = false;
         if constexpr (PPL == 1) {
             const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
-            j1 = (in_range && x < d.W && y < d.H) ? a.bins[(int64_t)y * d.W + x] : 0xFF;
+            j1 = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
             ballot_bins<SEG>(j1, cnt1, first1);
         } else {
 #pragma unroll 4
             for (int tt = 0; tt < PPL; ++tt) {
                 const int q = lane + tt * SEG;
                 const int x = ux * s + (q & (s - 1)), y = uy * s + (q >> level);
-                mine[q] = (in_range && x < d.W && y < d.H) ? a.bins[(int64_t)y * d.W + x] : 0xFF;
+                mine[q] = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
             }
             __syncthreads();
         }
@@ -366,9 +386,9 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                 target = accept ? bn : -1;
                 if (pass == 1) {
                     if (lane == 0) {
-                        a.pend[unit] = target;
+                        v.pend[unit] = target;
                         if (target >= 0)
-                            __hip_atomic_store(&a.src[k], (int32_t)stamp, __ATOMIC_RELAXED,
+                            __hip_atomic_store(&v.src[k], (int32_t)stamp, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                     }
                     target = -1;
@@ -378,20 +398,20 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
                 // apply (Sec. 5.3.3): the block's counts leave k and join target
                 if (lane == 0) {
                     units[(int64_t)uy * uw + ux] = target;
-                    table_add(a, t, W, mylog, (int32_t)(khs + target), (int32_t)m);
-                    table_add(a, t, W, mylog, (int32_t)(khs + k), -(int32_t)m);
+                    table_add(b, t, W, mylog, (int32_t)(v.base + khs + target), (int32_t)m);
+                    table_add(b, t, W, mylog, (int32_t)(v.base + khs + k), -(int32_t)m);
                 }
 #pragma unroll 4
                 for (int tt = 0; tt < PPL; ++tt) {
                     int j, cnt;
                     leader_bin(tt, j, cnt);
                     if (!cnt) continue;
-                    table_add(a, t, W, mylog, target * d.hs + j, cnt);
-                    table_add(a, t, W, mylog, k * d.hs + j, -cnt);
+                    table_add(b, t, W, mylog, (int32_t)(v.base + target * d.hs + j), cnt);
+                    table_add(b, t, W, mylog, (int32_t)(v.base + k * d.hs + j), -cnt);
                 }
             }
         } else if (in_range && pass == 1 && lane == 0) {
-            a.pend[unit] = -1;
+            v.pend[unit] = -1;
         }
         if constexpr (PPL > 1) __syncthreads();  // LDS staging is reused next round
     }
@@ -400,11 +420,11 @@ __device__ inline void block_phase(const RefineArgs &a, int level, int cls, int 
 // BIG = false instantiates block sides up to 8 only (levels <= 4): fewer
 // registers and no scratch for the common hierarchies.
 template <bool BIG>
-__device__ inline void block_phase_any(const RefineArgs &a, int level, int cls, int par, int pass,
-                                       uint32_t stamp, int32_t *units, uint8_t *sbin,
+__device__ inline void block_phase_any(const BatchArgs &b, const ImageView &v, int level, int cls,
+                                       int par, int pass, uint32_t stamp, uint8_t *sbin,
                                        DeltaTable &t, int2 *mylog) {
 #define SEEDS_BLOCK(SEG, PPL) \
-    block_phase<SEG, PPL>(a, level, cls, par, pass, stamp, units, sbin, t, mylog)
+    block_phase<SEG, PPL>(b, v, level, cls, par, pass, stamp, sbin, t, mylog)
     if (!BIG) {
         switch (level) {
             case 1: SEEDS_BLOCK(4, 1); break;
@@ -425,27 +445,19 @@ __device__ inline void block_phase_any(const RefineArgs &a, int level, int cls, 
 #undef SEEDS_BLOCK
 }
 
-// Level transition: every block of `level` splits into its 2x2 children.
-__device__ inline void descend(const RefineArgs &a, int level, int cur_bl) {
-    const Dims &d = a.d;
+// Level transition: every block of `level` splits into its 2x2 children
+// (into the pixel labels from level 1).
+__device__ inline void descend(const ImageView &v, int level) {
+    const Dims &d = v.d;
     const int fw = units_w(d, level);
-    const int32_t *from = pick(a.bl, cur_bl);
-    int32_t *to = level == 1 ? a.lab : pick(a.bl, cur_bl ^ 1);
+    const int32_t *from = level_grid(v, level);
+    int32_t *to = level == 1 ? v.lab : level_grid(v, level - 1);
     const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
     const int64_t n = (int64_t)tw * th;
-    for (int64_t i = (int64_t)xcd_group() * kPT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPT) {
+    for (int64_t i = (int64_t)v.grp * kPT + threadIdx.x; i < n; i += (int64_t)v.ngroups * kPT) {
         const int x = (int)(i % tw), y = (int)(i / tw);
         to[i] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
     }
-}
-
-// Upper bound on the log entries (deltas) one workgroup produces in one round
-// of a phase at `level`.
-__host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
-    if (level == 0) return 2 * kPT;
-    const int segs = kPT / seg_lanes(level);
-    const int bins = min(1 << (2 * level), d.nb);
-    return segs * (2 * bins + 2);
 }
 
 }  // namespace seeds

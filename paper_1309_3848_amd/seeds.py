@@ -38,6 +38,15 @@ class seeds_params(ctypes.Structure):
                 ("block_rule", ctypes.c_int32)]
 
 
+SEEDS_MAX_BATCH = 4096
+
+
+class seeds_image(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("row_pitch_bytes", ctypes.c_int64), ("num_superpixels", ctypes.c_int32),
+                ("levels", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -62,6 +71,13 @@ def lib() -> ctypes.CDLL:
             "seeds_level": ([P], I32),
             "seeds_set_launch_mode": ([P, I32], S),
             "seeds_sync": ([P, P], S),
+            "seeds_batch_init": ([ctypes.POINTER(P), ctypes.POINTER(seeds_image), I32,
+                                  ctypes.POINTER(seeds_params), P], S),
+            "seeds_batch_reinit": ([P, ctypes.POINTER(P), ctypes.POINTER(I64), P], S),
+            "seeds_batch_count": ([P], I32),
+            "seeds_batch_labels": ([P, I32, P, I32, P], S),
+            "seeds_batch_histograms": ([P, I32, P, P, I32, P], S),
+            "seeds_batch_num_superpixels": ([P, I32], I32),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -100,10 +116,7 @@ def seeds_grid(H: int, W: int, num_superpixels: int, levels: int):
 
 def seeds_init(rgb: torch.Tensor, num_superpixels: int, params: seeds_params, stream=None):
     """rgb: H x W x 3 uint8 CUDA tensor (rows may be strided). Returns a ctx handle."""
-    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or not rgb.is_cuda:
-        raise ValueError("rgb must be an H x W x 3 uint8 device tensor")
-    if rgb.stride(2) != 1 or rgb.stride(1) != 3:
-        raise ValueError("rgb pixels must be interleaved R,G,B bytes")
+    _check_rgb(rgb)
     H, W, _ = rgb.shape
     ctx = ctypes.c_void_p()
     _check(lib().seeds_init(ctypes.byref(ctx), rgb.data_ptr(), H, W, rgb.stride(0),
@@ -111,10 +124,75 @@ def seeds_init(rgb: torch.Tensor, num_superpixels: int, params: seeds_params, st
     return ctx
 
 
-def seeds_reinit(ctx, rgb: torch.Tensor, stream=None) -> None:
-    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or not rgb.is_cuda or rgb.stride(1) != 3:
+def _check_rgb(rgb: torch.Tensor) -> None:
+    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or not rgb.is_cuda:
         raise ValueError("rgb must be an H x W x 3 uint8 device tensor")
+    if rgb.stride(2) != 1 or rgb.stride(1) != 3:
+        raise ValueError("rgb pixels must be interleaved R,G,B bytes")
+
+
+def seeds_reinit(ctx, rgb: torch.Tensor, stream=None) -> None:
+    _check_rgb(rgb)
     _check(lib().seeds_reinit(ctx, rgb.data_ptr(), rgb.stride(0), _stream(stream)))
+
+
+def seeds_batch_init(images, num_superpixels, params: seeds_params, levels=None, stream=None):
+    """images: list of H x W x 3 uint8 device tensors; num_superpixels and
+    levels: one int for all images or one per image (levels default to
+    params.levels). Returns a ctx handle."""
+    n = len(images)
+    ks = list(num_superpixels) if hasattr(num_superpixels, "__len__") else [num_superpixels] * n
+    if levels is None:
+        levels = params.levels
+    ls = list(levels) if hasattr(levels, "__len__") else [levels] * n
+    if len(ks) != n or len(ls) != n:
+        raise ValueError("one num_superpixels and one levels value per image")
+    arr = (seeds_image * max(n, 1))()
+    for i, rgb in enumerate(images):
+        _check_rgb(rgb)
+        arr[i] = seeds_image(rgb.data_ptr(), rgb.shape[0], rgb.shape[1], rgb.stride(0), ks[i], ls[i])
+    ctx = ctypes.c_void_p()
+    _check(lib().seeds_batch_init(ctypes.byref(ctx), arr, n, ctypes.byref(params),
+                                  _stream(stream)))
+    return ctx
+
+
+def seeds_batch_reinit(ctx, images, stream=None) -> None:
+    n = len(images)
+    ptrs = (ctypes.c_void_p * max(n, 1))()
+    pitches = (ctypes.c_int64 * max(n, 1))()
+    for i, rgb in enumerate(images):
+        _check_rgb(rgb)
+        ptrs[i] = rgb.data_ptr()
+        pitches[i] = rgb.stride(0)
+    if n != seeds_batch_count(ctx):
+        raise ValueError(f"context holds {seeds_batch_count(ctx)} images, got {n}")
+    _check(lib().seeds_batch_reinit(ctx, ptrs, pitches, _stream(stream)))
+
+
+def seeds_batch_count(ctx) -> int:
+    return lib().seeds_batch_count(ctx)
+
+
+def seeds_batch_labels(ctx, image: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+    if out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor")
+    _check(lib().seeds_batch_labels(ctx, image, out.data_ptr(), 0 if out.is_cuda else 1,
+                                    _stream(stream)))
+    return out
+
+
+def seeds_batch_num_superpixels(ctx, image: int) -> int:
+    return lib().seeds_batch_num_superpixels(ctx, image)
+
+
+def seeds_batch_histograms(ctx, image: int, hist: torch.Tensor | None,
+                           size: torch.Tensor | None, stream=None):
+    host = _host_flag(hist, size)
+    _check(lib().seeds_batch_histograms(ctx, image, hist.data_ptr() if hist is not None else None,
+                                        size.data_ptr() if size is not None else None,
+                                        1 if host else 0, _stream(stream)))
+    return hist, size
 
 
 def seeds_refine(ctx, stream=None) -> None:
@@ -143,7 +221,7 @@ def seeds_level(ctx) -> int:
     return lib().seeds_level(ctx)
 
 
-def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, stream=None):
+def _host_flag(hist, size) -> bool:
     host = None
     for t in (hist, size):
         if t is not None:
@@ -152,6 +230,11 @@ def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, 
             host = (not t.is_cuda) if host is None else host
             if host != (not t.is_cuda):
                 raise ValueError("hist and size must both be on the device or both on the host")
+    return bool(host)
+
+
+def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, stream=None):
+    host = _host_flag(hist, size)
     _check(lib().seeds_histograms(ctx, hist.data_ptr() if hist is not None else None,
                                   size.data_ptr() if size is not None else None,
                                   1 if host else 0, _stream(stream)))

@@ -16,6 +16,7 @@ All draws come from numpy's PCG64 seeded with ``seed`` in a fixed order.
 from __future__ import annotations
 
 import hashlib
+import os
 
 import numpy as np
 from scipy.spatial import cKDTree
@@ -24,7 +25,8 @@ from scipy.spatial import cKDTree
 def _regions(H: int, W: int, sites: np.ndarray) -> np.ndarray:
     ys, xs = np.mgrid[0:H, 0:W]
     pts = np.stack([xs.ravel() + 0.5, ys.ravel() + 0.5], axis=1)
-    _, idx = cKDTree(sites).query(pts, k=1)
+    # nearest-site queries are independent per point: threads change nothing
+    _, idx = cKDTree(sites).query(pts, k=1, workers=min(8, os.cpu_count() or 1))
     return idx.reshape(H, W).astype(np.int32)
 
 

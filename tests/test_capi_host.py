@@ -128,3 +128,55 @@ def test_init_without_a_device_reports_device_error(S):
     assert st in (S.SEEDS_E_DEVICE, S.SEEDS_E_NOMEM)
     assert not ctx.value
     assert S.seeds_last_error()
+
+
+def _images(S, specs):
+    arr = (S.seeds_image * len(specs))()
+    for i, (H, W, K, L, pitch, ptr) in enumerate(specs):
+        arr[i] = S.seeds_image(ptr, H, W, pitch, K, L)
+    return arr
+
+
+@pytest.mark.parametrize("specs,count,msg", [
+    ([], 0, "batch of 0"),
+    ([(16, 16, 4, 2, 48, 1 << 20)], 4097, "batch of 4097"),
+    ([(16, 16, 4, 2, 48, 1 << 20), (16, 16, 4, 2, 48, 0)], 2, "image 1: rgb"),
+    ([(16, 16, 4, 2, 48, 1 << 20), (16, 16, 4, 2, 47, 1 << 20)], 2, "image 1: row pitch"),
+    ([(16, 16, 4, 9, 48, 1 << 20)], 1, "image 0: levels 9"),
+    ([(16, 16, 4, 2, 48, 1 << 20), (0, 16, 4, 2, 48, 1 << 20)], 2, "image 1: image size"),
+    ([(16, 16, 4, 2, 48, 1 << 20), (16, 16, 400, 2, 48, 1 << 20)], 2, "image 1: "),
+])
+def test_batch_init_rejects_bad_images_before_device_work(S, specs, count, msg):
+    p = S.make_params()
+    ctx = ctypes.c_void_p()
+    arr = _images(S, specs) if specs else None
+    st = S.lib().seeds_batch_init(ctypes.byref(ctx), arr, count, ctypes.byref(p), None)
+    assert st == S.SEEDS_E_INVAL
+    assert not ctx.value
+    assert msg in S.seeds_last_error()
+
+
+def test_batch_null_arguments(S):
+    L = S.lib()
+    p = S.make_params()
+    arr = _images(S, [(16, 16, 4, 2, 48, 1 << 20)])
+    assert L.seeds_batch_init(None, arr, 1, ctypes.byref(p), None) == S.SEEDS_E_INVAL
+    ctx = ctypes.c_void_p()
+    assert L.seeds_batch_init(ctypes.byref(ctx), arr, 1, None, None) == S.SEEDS_E_INVAL
+    assert L.seeds_batch_reinit(None, None, None, None) == S.SEEDS_E_INVAL
+    assert L.seeds_batch_labels(None, 0, None, 0, None) == S.SEEDS_E_INVAL
+    assert L.seeds_batch_histograms(None, 0, None, None, 0, None) == S.SEEDS_E_INVAL
+    assert L.seeds_batch_num_superpixels(None, 0) == -1
+    assert L.seeds_batch_count(None) == -1
+
+
+def test_batch_init_without_a_device_reports_device_error(S):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = S.make_params(levels=2)
+    arr = _images(S, [(16, 16, 4, 2, 48, 1 << 20), (20, 24, 6, 1, 72, 1 << 21)])
+    ctx = ctypes.c_void_p()
+    st = S.lib().seeds_batch_init(ctypes.byref(ctx), arr, 2, ctypes.byref(p), None)
+    assert st in (S.SEEDS_E_DEVICE, S.SEEDS_E_NOMEM)
+    assert not ctx.value
