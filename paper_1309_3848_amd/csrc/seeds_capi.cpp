@@ -400,7 +400,8 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     ctx->top = in[0].d;
     for (const auto &im : in) ctx->top.L = std::max(ctx->top.L, im.d.L);
     const int Lmax = ctx->top.L;
-    // offsets of every image in the arenas
+    // offsets of every image in the arenas; image 0 starts every arena at
+    // offset 0, which the single-image kernels rely on
     size_t bins = 0, lab = 0, bl = 0, state = 0, src = 0, pend = 0;
     for (const auto &im : in) {
         const Dims &d = im.d;

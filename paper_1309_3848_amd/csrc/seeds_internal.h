@@ -140,9 +140,11 @@ __host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
 }
 
 // Workgroups of one descend launch for an image and of one init launch.
+// A descend workgroup writes one row (a chunk of up to 256 units) of the
+// child grid.
 __host__ __device__ inline int descend_groups(const Dims &d, int level) {
-    const int64_t n = (int64_t)units_w(d, level - 1) * units_h(d, level - 1);
-    return (int)((n + kPersistentThreads - 1) / kPersistentThreads);
+    const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
+    return th * ((tw + kPersistentThreads - 1) / kPersistentThreads);
 }
 constexpr int kInitTW = 64, kInitTH = 16;
 __host__ __device__ inline int init_groups(const Dims &d) {

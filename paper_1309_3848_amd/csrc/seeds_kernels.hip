@@ -127,13 +127,13 @@ __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
 // ---------------------------------------------------------------------------
 // Pixel labels of one image from a block grid of a level (output of a state
 // stopped at a block level).
+// One workgroup per (row, chunk of kThreads columns).
 __global__ __launch_bounds__(kThreads) void k_expand(const int32_t *__restrict__ blab, int uw,
-                                                     int level, int W, int H,
+                                                     int level, int W, int chunks,
                                                      int32_t *__restrict__ out) {
-    const int64_t i = (int64_t)xcd_group() * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)W * H) return;
-    const int x = (int)(i % W), y = (int)(i / W);
-    out[i] = blab[(int64_t)(y >> level) * uw + (x >> level)];
+    const int it = xcd_group();
+    const int y = it / chunks, x = (it - y * chunks) * kThreads + (int)threadIdx.x;
+    if (x < W) out[(int64_t)y * W + x] = blab[(int64_t)(y >> level) * uw + (x >> level)];
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -157,9 +157,9 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
 
 hipError_t launch_expand(const Dims &d, const int32_t *blab, int level, int32_t *out,
                          hipStream_t s) {
-    const int64_t n = (int64_t)d.W * d.H;
-    hipLaunchKernelGGL(k_expand, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, blab,
-                       units_w(d, level), level, d.W, d.H, out);
+    const int chunks = (int)blocks_for(d.W, kThreads);
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)(chunks * d.H)), dim3(kThreads), 0, s, blab,
+                       units_w(d, level), level, d.W, chunks, out);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
     __shared__ int s_prev_n;
     const BatchArgs &b = a.b;
     const Dims &d = a.one.d;
-    const ImageView v = make_view(b, a.one, xcd_group(), gridDim.x);
+    const ImageView v = single_view(b, a.one, xcd_group(), gridDim.x);
     uint32_t *sync = b.ar.sync;
     uint32_t gen = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int2 *const log0 = b.ar.log + (int64_t)blockIdx.x * b.log_cap;

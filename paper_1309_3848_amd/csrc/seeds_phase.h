@@ -36,7 +36,8 @@ struct ImageView {
     Dims d;
     const uint8_t *bins;
     int32_t *lab;
-    int32_t *bl0, *bl1;  // block grids of this image (level l in bl[l % 2])
+    int32_t *bl;         // block grid buffer 0 of this image; level l is in
+    int64_t bl_step;     // buffer l % 2, at bl + (l % 2) * bl_step
     int64_t base;        // global index of this image's state in a state copy
     int32_t *src;
     int32_t *pend;
@@ -44,8 +45,10 @@ struct ImageView {
     int ngroups;         // the image's workgroups in this launch
 };
 
+// Selected by arithmetic, not by choosing between two struct fields, which
+// the compiler may turn into an indexed load from a stack copy (scratch).
 __device__ __forceinline__ int32_t *level_grid(const ImageView &v, int level) {
-    return (level & 1) ? v.bl1 : v.bl0;
+    return v.bl + (level & 1) * v.bl_step;
 }
 
 __device__ __forceinline__ ImageView make_view(const BatchArgs &b, const ImageDesc &g, int grp,
@@ -54,11 +57,30 @@ __device__ __forceinline__ ImageView make_view(const BatchArgs &b, const ImageDe
     v.d = g.d;
     v.bins = b.ar.bins + g.bins;
     v.lab = b.ar.lab + g.lab;
-    v.bl0 = b.ar.bl + g.bl[0];
-    v.bl1 = b.ar.bl + g.bl[1];
+    v.bl = b.ar.bl + g.bl[0];
+    v.bl_step = g.bl[1] - g.bl[0];
     v.base = g.state;
     v.src = b.ar.src + g.src;
     v.pend = b.ar.pend + g.pend;
+    v.grp = grp;
+    v.ngroups = ngroups;
+    return v;
+}
+
+// View of the only image of a single-image context: its offsets into the
+// arenas are all zero (the context lays it out first), so the view needs no
+// offset arithmetic and its state base is the constant 0.
+__device__ __forceinline__ ImageView single_view(const BatchArgs &b, const ImageDesc &g, int grp,
+                                                 int ngroups) {
+    ImageView v;
+    v.d = g.d;
+    v.bins = b.ar.bins;
+    v.lab = b.ar.lab;
+    v.bl = b.ar.bl;
+    v.bl_step = g.bl[1];
+    v.base = 0;
+    v.src = b.ar.src;
+    v.pend = b.ar.pend;
     v.grp = grp;
     v.ngroups = ngroups;
     return v;
@@ -453,10 +475,12 @@ __device__ inline void descend(const ImageView &v, int level) {
     const int32_t *from = level_grid(v, level);
     int32_t *to = level == 1 ? v.lab : level_grid(v, level - 1);
     const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
-    const int64_t n = (int64_t)tw * th;
-    for (int64_t i = (int64_t)v.grp * kPT + threadIdx.x; i < n; i += (int64_t)v.ngroups * kPT) {
-        const int x = (int)(i % tw), y = (int)(i / tw);
-        to[i] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
+    // work item = (child row, chunk of kPT columns): no per-lane division
+    const int chunks = (tw + kPT - 1) / kPT;
+    const int items = th * chunks;
+    for (int it = v.grp; it < items; it += v.ngroups) {
+        const int y = it / chunks, x = (it - y * chunks) * kPT + (int)threadIdx.x;
+        if (x < tw) to[(int64_t)y * tw + x] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
     }
 }
 

@@ -8,18 +8,24 @@
 namespace seeds {
 namespace {
 
-// Image and rank of this workgroup. A single image needs no lookup; in a
-// batch, map[logical group] = (image, rank among the image's workgroups).
+// Image and rank of this workgroup. A single image (BATCH = false) takes its
+// view straight from the kernel arguments, so the compiler can reload any of
+// its fields instead of keeping them all live; in a batch, map[logical
+// group] = (image, rank among the image's workgroups).
+template <bool BATCH>
 __device__ __forceinline__ ImageView resolve(const BatchArgs &b, const ImageDesc &one,
                                              const int2 *map, int level, int cls) {
     const int lg = xcd_group();
-    if (b.nimg == 1) return make_view(b, one, lg, gridDim.x);
-    const int2 e = map[lg];
-    const ImageDesc g = b.imgs[e.x];
-    return make_view(b, g, e.y, phase_groups(g.d, level, cls));
+    if constexpr (!BATCH) {
+        return single_view(b, one, lg, gridDim.x);
+    } else {
+        const int2 e = map[lg];
+        const ImageDesc g = b.imgs[e.x];
+        return make_view(b, g, e.y, phase_groups(g.d, level, cls));
+    }
 }
 
-template <bool BIG>
+template <bool BIG, bool BATCH>
 __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const int2 *map,
                                                int level, int cls, int par, int pass,
                                                uint32_t stamp, int replay_groups) {
@@ -43,7 +49,7 @@ __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const
         pre_n = b.ar.log_n[own_slot];
         if (threadIdx.x < kPre) pre = b.ar.log[own_slot * b.log_cap + threadIdx.x];
     }
-    const ImageView v = resolve(b, one, map, level, cls);
+    const ImageView v = resolve<BATCH>(b, one, map, level, cls);
     int2 *mylog = b.ar.log + ((int64_t)par * b.log_groups + blockIdx.x) * b.log_cap;
     if (level == 0)
         pixel_phase(b, v, cls, par, t, mylog, pl);
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(kPT) void k_descend(BatchArgs b, ImageDesc one, con
                                                  int level) {
     const int lg = xcd_group();
     if (b.nimg == 1) {
-        descend(make_view(b, one, lg, gridDim.x), level);
+        descend(single_view(b, one, lg, gridDim.x), level);
         return;
     }
     const int2 e = map[lg];
@@ -106,12 +112,11 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
                         int replay_groups, hipStream_t s) {
     const int lds = level == 0 ? 0 : kPT * seg_ppl(level);
-    if (max_level >= 4)
-        hipLaunchKernelGGL(k_phase<true>, dim3(groups), dim3(kPT), lds, s, b, one, map, level,
-                           cls, par, pass, stamp, replay_groups);
-    else
-        hipLaunchKernelGGL(k_phase<false>, dim3(groups), dim3(kPT), lds, s, b, one, map, level,
-                           cls, par, pass, stamp, replay_groups);
+    const bool batch = b.nimg > 1;
+    auto fn = max_level >= 4 ? (batch ? k_phase<true, true> : k_phase<true, false>)
+                             : (batch ? k_phase<false, true> : k_phase<false, false>);
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, one, map, level, cls, par, pass,
+                       stamp, replay_groups);
     return hipGetLastError();
 }
 
