@@ -11,6 +11,14 @@ Prop. 1 block rule.
 Prints one JSON line (rank 0). `roofline` reports the refine kernel against
 the HBM roofline with the algorithmic bytes of the schedule; `cpu_baseline`
 times the CPU oracle on the same image and checks the GPU labels against it.
+
+`--workload batch64` measures the mixed batch instead: 64 synthetic images,
+W ~ U{320..1920}, H ~ U{240..1080}, 50-600 Voronoi regions, noise sigma in
+[4,16], K ~ U{200..2000} clamped to N/256, 3-4 levels, 5 bins, 4 sweeps,
+gamma 1, Prop. 1 rule, refined by one batch context (one launch per phase for
+all images). A step re-initialises all 64 images, refines them and writes
+their labels to device buffers. The line also reports the same images run
+one after another through single-image contexts (the plain path).
 """
 from __future__ import annotations
 
@@ -82,11 +90,152 @@ def measured_traffic():
     return t.get("traffic_bytes_per_launch")
 
 
+def _percentiles(lat):
+    lat = sorted(lat)
+    return lat[len(lat) // 2], lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+
+
+def run_batch(args) -> int:
+    import numpy as np
+    import torch
+
+    from paper_1309_3848_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build(force=True)
+    from paper_1309_3848_amd import seeds as S
+    from paper_1309_3848_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    specs = synth.batch_mixed(64)
+    imgs = [synth.voronoi_image(s["H"], s["W"], s["regions"], s["sigma"], s["seed"])
+            for s in specs]
+    rgbs = [torch.from_numpy(im).to(dev) for im in imgs]
+    Ks = [s["K"] for s in specs]
+    Ls = [s["levels"] for s in specs]
+    npx = sum(s["H"] * s["W"] for s in specs)
+    outs = [torch.empty((s["H"], s["W"]), dtype=torch.int32, device=dev) for s in specs]
+    stream = torch.cuda.current_stream()
+    params = S.make_params(max(Ls), BINS, ITERS, GAMMA, RULE)
+    ctx = S.seeds_batch_init(rgbs, Ks, params, levels=Ls, stream=stream)
+
+    def step():
+        S.seeds_batch_reinit(ctx, rgbs, stream)
+        S.seeds_refine(ctx, stream)
+        for i in range(len(specs)):
+            S.seeds_batch_labels(ctx, i, outs[i], stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p50, p99 = _percentiles([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    ms_per_step = wall * 1e3 / args.steps
+
+    reps = max(5, args.steps // 2)
+    r0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    r1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for i in range(reps):
+        S.seeds_batch_reinit(ctx, rgbs, stream)
+        r0[i].record(stream)
+        S.seeds_refine(ctx, stream)
+        r1[i].record(stream)
+    for i in range(len(specs)):
+        S.seeds_batch_labels(ctx, i, outs[i], stream)
+    torch.cuda.synchronize()
+    refine_ms = sum(a.elapsed_time(b) for a, b in zip(r0, r1)) / reps
+    S.seeds_sync(ctx, stream)
+    S.seeds_destroy(ctx)
+    gpu_labels = [o.cpu().numpy() for o in outs]
+
+    # the plain path: the same images through single-image contexts, in turn
+    solo = [S.seeds_init(r, k, S.make_params(l, BINS, ITERS, GAMMA, RULE), stream)
+            for r, k, l in zip(rgbs, Ks, Ls)]
+
+    def solo_step():
+        for c, r, o in zip(solo, rgbs, outs):
+            S.seeds_reinit(c, r, stream)
+            S.seeds_refine(c, stream)
+            S.seeds_labels(c, o, stream)
+
+    for _ in range(max(2, args.warmup // 4)):
+        solo_step()
+    torch.cuda.synchronize()
+    solo_steps = max(3, args.steps // 4)
+    t1 = time.perf_counter()
+    for _ in range(solo_steps):
+        solo_step()
+    torch.cuda.synchronize()
+    solo_ms = (time.perf_counter() - t1) * 1e3 / solo_steps
+    solo_same = all(bool(np.array_equal(o.cpu().numpy(), g)) for o, g in zip(outs, gpu_labels))
+    for c in solo:
+        S.seeds_destroy(c)
+
+    # algorithmic bytes of all phase launches (each image over its own levels)
+    launches = max(Ls) * ITERS * 9
+    refine_bytes = sum(schedule_bytes(s["H"], s["W"], s["levels"], ITERS)[1] for s in specs)
+    per_launch = refine_bytes / launches
+    phase_us = refine_ms * 1e3 / launches
+    achieved = per_launch / (phase_us * 1e-6) / 1e9
+    result = {
+        "metric": METRIC, "value": round(npx * args.steps / wall / 1e6, 2), "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch of 64 mixed RGB u8 images (W 320-1920, H 240-1080, "
+                               "50-600 Voronoi regions, noise sigma 4-16, seeds 3000+i); K 200-2000 "
+                               "clamped to N/256, 3-4 levels, 5 bins/channel, 4 sweeps/level, "
+                               "gamma 1, Prop. 1 block rule; one batch context",
+                   "images": len(specs), "megapixels": round(npx / 1e6, 3),
+                   "step": "batch reinit + refine + labels of every image (device)"},
+        "p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
+        "images_per_s": round(len(specs) * args.steps / wall, 1),
+        "plain_path": {"ms_per_batch": round(solo_ms, 4),
+                       "value": round(npx / (solo_ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                       "labels_equal_to_batch": solo_same},
+        "roofline": {"bound": "hbm", "kernel": "k_phase (batch variant; one phase of every "
+                                               "image per launch)",
+                     "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(per_launch),
+                     "launches_per_batch": launches, "avg_launch_us": round(phase_us, 3),
+                     "refine_ms": round(refine_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        order = np.argsort([s["H"] * s["W"] for s in specs])
+        sample = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+        t2 = time.perf_counter()
+        px, same = 0, True
+        for i in sample:
+            ref, _, _ = oracle.seeds(imgs[i], Ks[i], Ls[i], BINS, ITERS, GAMMA, RULE)
+            px += imgs[i].shape[0] * imgs[i].shape[1]
+            same &= bool(np.array_equal(gpu_labels[i], ref))
+        cpu_s = time.perf_counter() - t2
+        result["cpu_baseline"] = {
+            "value": round(px / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"images {sample} of the batch (smallest, median, largest), full runs, "
+                      f"single-threaded C oracle, {cpu_s:.1f} s"}
+        result["bitexact_vs_oracle"] = same
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=["single1080p", "batch64"], default="single1080p")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,8 +244,14 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(images are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(images are independent: several GPUs would each refine their own images)", file=sys.stderr)
         return 2
+    if args.workload == "batch64":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 3 if args.warmup is None else args.warmup
+        return run_batch(args)
+    args.steps = 200 if args.steps is None else args.steps
+    args.warmup = 20 if args.warmup is None else args.warmup
 
     import numpy as np
     import torch
@@ -143,9 +298,7 @@ def main() -> int:
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
-    p50 = lat[len(lat) // 2]
-    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+    p50, p99 = _percentiles([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_per_step = wall * 1e3 / args.steps
     mpx = H * W * args.steps / wall / 1e6
 

@@ -159,6 +159,21 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  * same check.                                                                */
 seeds_status seeds_sync(seeds_ctx *ctx, void *hip_stream);
 
+/* ---- Streams ------------------------------------------------------------
+ * Warm start for the next frame of a video stream (the paper names video as
+ * an input the framework adapts to, Sec. 7, and its refinement can stop and
+ * resume at any time, Sec. 5.4). The context keeps the previous frame's pixel
+ * labels; the call bins the new frame (Sec. 4.1), recounts every
+ * superpixel's colour histogram and size from those labels (eq.
+ * eqColorHistogram) and marks the schedule finished, so that the next
+ * seeds_refine runs I pixel-level sweeps on the new frame.
+ *   rgb, row_pitch_bytes  as for seeds_init (same H and W as the context);
+ *                         read in stream order.
+ * SEEDS_E_STATE unless the labels are at pixel level (refine the first frame
+ * to the end first). No allocation.                                          */
+seeds_status seeds_warm_start(seeds_ctx *ctx, const uint8_t *rgb, int64_t row_pitch_bytes,
+                              void *hip_stream);
+
 /* ---- Batches ------------------------------------------------------------
  * A batch context refines several independent images together: each image
  * gets exactly the labels, histograms and sizes that a single-image context
@@ -200,6 +215,12 @@ seeds_status seeds_batch_init(seeds_ctx **out, const seeds_image *images, int32_
  * enqueues only.                                                             */
 seeds_status seeds_batch_reinit(seeds_ctx *ctx, const uint8_t *const *rgb,
                                 const int64_t *row_pitch_bytes, void *hip_stream);
+
+/* seeds_warm_start for every image of a batch context: rgb[i] and
+ * row_pitch_bytes[i] as for seeds_batch_reinit (waits for the stream when a
+ * pointer or pitch changed).                                                 */
+seeds_status seeds_batch_warm_start(seeds_ctx *ctx, const uint8_t *const *rgb,
+                                    const int64_t *row_pitch_bytes, void *hip_stream);
 
 /* Number of images of the context (1 for seeds_init contexts; -1 for NULL). */
 int32_t seeds_batch_count(const seeds_ctx *ctx);

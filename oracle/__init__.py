@@ -56,6 +56,8 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_free.argtypes = [P]
     L.oracle_set_pixel_labels.argtypes = [P, P]
     L.oracle_set_pixel_labels.restype = I32
+    L.oracle_warm_start.argtypes = [P, P, ctypes.c_int64]
+    L.oracle_warm_start.restype = I32
     L.oracle_set_unit_labels.argtypes = [P, I32, P]
     L.oracle_set_unit_labels.restype = I32
     L.oracle_decide_class.argtypes = [P, I32, P, I32]
@@ -159,6 +161,14 @@ class Oracle:
         assert lab.shape == (self.H, self.W)
         if self._L.oracle_set_pixel_labels(self._h, _ptr(lab)) != 0:
             raise ValueError("label out of range")
+
+    def warm_start(self, rgb: np.ndarray) -> None:
+        """Next frame of a stream: keep the pixel labels, bin the new frame,
+        recount; the next run() does I pixel sweeps."""
+        img = np.ascontiguousarray(rgb, dtype=np.uint8)
+        assert img.shape == (self.H, self.W, 3)
+        if self._L.oracle_warm_start(self._h, _ptr(img), self.W * 3) != 0:
+            raise ValueError("warm start needs a state at pixel level")
 
     def set_unit_labels(self, level: int, labels: np.ndarray) -> None:
         lab = np.ascontiguousarray(labels, dtype=np.int32)

@@ -202,6 +202,22 @@ int oracle_set_pixel_labels(oracle_state *st, const int32_t *labels) {
     return 0;
 }
 
+/* Warm start on the next frame of a stream. The paper names video as an
+ * input the framework adapts to (Sec. 7) and lets the refinement stop and
+ * resume at any time (Sec. 5.4); the reading taken here: keep the pixel
+ * labels of the previous frame, bin the new frame (Sec. 4.1), recount the
+ * colour histograms and sizes of every superpixel from those labels and bins
+ * (eq. eqColorHistogram), and mark the schedule finished, so that the next
+ * run does I pixel-level sweeps. Only a state at pixel level can be warm
+ * started (returns -1 otherwise).                                       */
+int oracle_warm_start(oracle_state *st, const uint8_t *rgb, int64_t pitch) {
+    if (st->level != 0) return -1;
+    oracle_quantise(rgb, st->H, st->W, pitch, st->B, st->bin);
+    recount(st);
+    st->cur_level = -1; st->cur_sweep = 0; st->cur_class = 0; st->cold = 0;
+    return 0;
+}
+
 /* Replace the partition by arbitrary labels on the unit grid of a level
  * (level 0 = pixels) and recount; the schedule then continues from the
  * first phase of that level.                                            */

@@ -609,6 +609,68 @@ seeds_status histograms_of(seeds_ctx *ctx, int32_t image, int32_t *hist, int32_t
     return SEEDS_OK;
 }
 
+// Take new image pointers and pitches (checked) for the next init or warm
+// start. A batch keeps them in device tables, re-uploaded only on change.
+seeds_status set_images(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t *row_pitch_bytes,
+                        hipStream_t s) {
+    if (!rgb || !row_pitch_bytes) return fail(SEEDS_E_INVAL, "image tables are NULL");
+    bool changed = false;
+    for (int i = 0; i < ctx->nimg; ++i) {
+        if (!rgb[i]) return fail(SEEDS_E_INVAL, "image %d: rgb is NULL", i);
+        if (row_pitch_bytes[i] < 3 * (int64_t)ctx->imgs[i].d.W)
+            return fail(SEEDS_E_INVAL, "image %d: row pitch %lld < 3 W", i,
+                        (long long)row_pitch_bytes[i]);
+        changed |= rgb[i] != ctx->rgb[i] || row_pitch_bytes[i] != ctx->pitch[i];
+    }
+    if (changed && ctx->nimg > 1) {
+        // the device tables are read by earlier init launches and copied from
+        // the host vectors in stream order: let both finish first
+        hipError_t e = hipStreamSynchronize(ctx->last_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return device_error(ctx, e, "synchronise");
+        for (int i = 0; i < ctx->nimg; ++i) {
+            ctx->rgb[i] = rgb[i];
+            ctx->pitch[i] = row_pitch_bytes[i];
+        }
+        e = hipMemcpyAsync((void *)ctx->d_rgb, ctx->rgb.data(), ctx->rgb.size() * sizeof(void *),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->d_pitch, ctx->pitch.data(), ctx->pitch.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return device_error(ctx, e, "image table upload");
+    } else if (changed) {
+        ctx->rgb[0] = rgb[0];
+        ctx->pitch[0] = row_pitch_bytes[0];
+    }
+    return SEEDS_OK;
+}
+
+// Warm start (a new frame of every image of the context): bins from the new
+// pixels, histograms and sizes recounted from the current pixel labels, and
+// the schedule marked finished so that the next refine runs I pixel sweeps.
+seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t *pitch,
+                        hipStream_t s) {
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    if (ctx->sched.level != 0)
+        return fail(SEEDS_E_STATE, "warm start needs pixel labels: the context is at level %d "
+                                   "(refine the first frame to the end)", ctx->sched.level);
+    st = set_images(ctx, rgb, pitch, s);
+    if (st != SEEDS_OK) return st;
+    const LaunchMap m = init_launch(ctx);
+    hipError_t e = launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
+    if (e == hipSuccess)
+        e = launch_rehist(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
+                          ctx->d_rgb, ctx->d_pitch, m.groups, s);
+    if (e != hipSuccess) return device_error(ctx, e, "warm start launch");
+    ctx->sched.cur_level = -1;
+    ctx->sched.cur_sweep = 0;
+    ctx->sched.cur_class = 0;
+    ctx->cold = false;
+    ctx->last_stream = s;
+    return SEEDS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -699,37 +761,23 @@ seeds_status seeds_batch_reinit(seeds_ctx *ctx, const uint8_t *const *rgb,
                                 const int64_t *row_pitch_bytes, void *hip_stream) {
     seeds_status st = check_usable(ctx);
     if (st != SEEDS_OK) return st;
-    if (!rgb || !row_pitch_bytes) return fail(SEEDS_E_INVAL, "image tables are NULL");
-    bool changed = false;
-    for (int i = 0; i < ctx->nimg; ++i) {
-        if (!rgb[i]) return fail(SEEDS_E_INVAL, "image %d: rgb is NULL", i);
-        if (row_pitch_bytes[i] < 3 * (int64_t)ctx->imgs[i].d.W)
-            return fail(SEEDS_E_INVAL, "image %d: row pitch %lld < 3 W", i,
-                        (long long)row_pitch_bytes[i]);
-        changed |= rgb[i] != ctx->rgb[i] || row_pitch_bytes[i] != ctx->pitch[i];
-    }
-    hipStream_t s = (hipStream_t)hip_stream;
-    if (changed && ctx->nimg > 1) {
-        // the device tables are read by earlier init launches and copied from
-        // the host vectors in stream order: let both finish first
-        hipError_t e = hipStreamSynchronize(ctx->last_stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return device_error(ctx, e, "synchronise");
-        for (int i = 0; i < ctx->nimg; ++i) {
-            ctx->rgb[i] = rgb[i];
-            ctx->pitch[i] = row_pitch_bytes[i];
-        }
-        e = hipMemcpyAsync((void *)ctx->d_rgb, ctx->rgb.data(), ctx->rgb.size() * sizeof(void *),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(ctx->d_pitch, ctx->pitch.data(), ctx->pitch.size() * sizeof(int64_t),
-                               hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return device_error(ctx, e, "image table upload");
-    } else if (changed) {
-        ctx->rgb[0] = rgb[0];
-        ctx->pitch[0] = row_pitch_bytes[0];
-    }
-    return start_schedule(ctx, s);
+    st = set_images(ctx, rgb, row_pitch_bytes, (hipStream_t)hip_stream);
+    if (st != SEEDS_OK) return st;
+    return start_schedule(ctx, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_warm_start(seeds_ctx *ctx, const uint8_t *rgb, int64_t row_pitch_bytes,
+                              void *hip_stream) {
+    if (!ctx) return fail(SEEDS_E_INVAL, "ctx is NULL");
+    if (ctx->nimg != 1)
+        return fail(SEEDS_E_INVAL, "context holds %d images: use seeds_batch_warm_start",
+                    ctx->nimg);
+    return warm_start(ctx, &rgb, &row_pitch_bytes, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_batch_warm_start(seeds_ctx *ctx, const uint8_t *const *rgb,
+                                    const int64_t *row_pitch_bytes, void *hip_stream) {
+    return warm_start(ctx, rgb, row_pitch_bytes, (hipStream_t)hip_stream);
 }
 
 seeds_status seeds_refine_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *phases_done,

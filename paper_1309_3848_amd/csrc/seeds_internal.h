@@ -183,6 +183,12 @@ hipError_t launch_descend(const BatchArgs &b, const ImageDesc &one, const int2 *
 // Sizes from the histograms of one image (pixel phases do not maintain them).
 hipError_t launch_sizes(const Dims &d, int32_t *state0, int32_t *state1, hipStream_t s);
 // Pixel labels of one image from the unit grid of `level`.
+// Warm start: bins from new frames and histograms and sizes recounted from
+// the current pixel labels (both state copies must be zero). Same workgroup
+// map and tables as launch_init.
+hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
+                         int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
+                         const int64_t *pitch_table, int groups, hipStream_t s);
 hipError_t launch_expand(const Dims &d, const int32_t *units, int level, int32_t *out,
                          hipStream_t s);
 

@@ -1,5 +1,5 @@
 // SEEDS kernels for gfx950: fills, initialisation (quantise, grid,
-// histograms) and level transitions. The phases themselves are in
+// histograms), the warm start of a stream frame and label expansion. The phases themselves are in
 // seeds_phase.hip (one launch per phase) and seeds_persistent.hip (one
 // launch per refinement).
 #include "seeds_device.h"
@@ -125,6 +125,134 @@ __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
 }
 
 // ---------------------------------------------------------------------------
+// Warm start on a new frame: bins of every pixel from the new frame (Sec.
+// 4.1) and the colour histograms and sizes of the superpixels from the labels
+// the pixels already carry (eq. eqColorHistogram).
+//
+// A workgroup covers a 64 x 16 pixel tile, as in the initialisation, but the
+// labels are arbitrary: the tile's distinct labels are first collected in a
+// small LDS hash table, each gets an LDS histogram slot, the pixels are
+// counted there and every non-zero count is merged once. Labels beyond the
+// table or the slots (tiny superpixels) go straight to global atomics.
+constexpr int kRehistKeys = 64, kRehistSlots = 32;
+
+struct RehistLds {
+    int32_t key[kRehistKeys];   // label, or -1
+    int32_t slot[kRehistKeys];  // histogram slot of the label, or -1 (global)
+    int32_t nslots;
+    int32_t hist[kRehistSlots * kMaxHs];
+    int32_t size[kRehistSlots];
+    int32_t label[kRehistSlots];
+};
+
+// Entry of label k in the key table (inserting it when `insert`), or -1.
+__device__ __forceinline__ int rehist_entry(RehistLds &r, int32_t k, bool insert) {
+    uint32_t h = ((uint32_t)k * 2654435761u) >> 26;  // 6 bits
+#pragma nounroll
+    for (int p = 0; p < kRehistKeys; ++p, h = (h + 1) & (kRehistKeys - 1)) {
+        const int32_t cur = insert ? atomicCAS(&r.key[h], -1, k) : r.key[h];
+        if (cur == k || (insert && cur == -1)) return (int)h;
+        if (cur == -1) return -1;
+    }
+    return -1;
+}
+
+constexpr int kRehistPx = kInitTW * kInitTH / kThreads;  // pixels per thread
+
+__device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
+                            uint8_t *__restrict__ bins, const int32_t *__restrict__ lab,
+                            int32_t *__restrict__ st0, int32_t *__restrict__ st1, int tile,
+                            RehistLds &r) {
+    const int64_t khs = (int64_t)d.K * d.hs;
+    const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
+    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * kInitTH;
+    for (int i = threadIdx.x; i < kRehistKeys; i += kThreads) {
+        r.key[i] = -1;
+        r.slot[i] = -1;
+    }
+    if (threadIdx.x == 0) r.nslots = 0;
+    __syncthreads();
+    // the thread's pixels: bins (written now) and labels, kept in registers
+    int32_t k[kRehistPx], j[kRehistPx];
+    const int x = x0 + (int)(threadIdx.x % kInitTW);
+#pragma unroll
+    for (int q = 0; q < kRehistPx; ++q) {
+        const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
+        k[q] = -1;
+        j[q] = 0;
+        if (x < d.W && y < d.H) {
+            const uint8_t *p = rgb + (int64_t)y * pitch + 3 * (int64_t)x;
+            j[q] = (((p[0] * d.B) >> 8) * d.B + ((p[1] * d.B) >> 8)) * d.B + ((p[2] * d.B) >> 8);
+            bins[(int64_t)y * d.W + x] = (uint8_t)j[q];
+            k[q] = lab[(int64_t)y * d.W + x];
+            rehist_entry(r, k[q], true);
+        }
+    }
+    __syncthreads();
+    // a slot per distinct label while slots last
+    for (int i = threadIdx.x; i < kRehistKeys; i += kThreads) {
+        if (r.key[i] < 0) continue;
+        const int s = atomicAdd(&r.nslots, 1);
+        if (s < kRehistSlots) {
+            r.slot[i] = s;
+            r.label[s] = r.key[i];
+        }
+    }
+    __syncthreads();
+    const int ns = min(r.nslots, kRehistSlots);
+    for (int i = threadIdx.x; i < ns * d.hs; i += kThreads) r.hist[i] = 0;
+    for (int i = threadIdx.x; i < ns; i += kThreads) r.size[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRehistPx; ++q) {
+        if (k[q] < 0) continue;
+        const int e = rehist_entry(r, k[q], false);
+        const int s = e >= 0 ? r.slot[e] : -1;
+        if (s >= 0) {
+            atomicAdd(&r.hist[s * d.hs + j[q]], 1);
+            atomicAdd(&r.size[s], 1);
+        } else {
+            atomicAdd(&st0[(int64_t)k[q] * d.hs + j[q]], 1);
+            atomicAdd(&st0[khs + k[q]], 1);
+            atomicAdd(&st1[(int64_t)k[q] * d.hs + j[q]], 1);
+            atomicAdd(&st1[khs + k[q]], 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ns * d.hs; i += kThreads) {
+        const int v = r.hist[i];
+        if (!v) continue;
+        const int s = i / d.hs, jj = i - s * d.hs;
+        atomicAdd(&st0[(int64_t)r.label[s] * d.hs + jj], v);
+        atomicAdd(&st1[(int64_t)r.label[s] * d.hs + jj], v);
+    }
+    for (int i = threadIdx.x; i < ns; i += kThreads) {
+        const int v = r.size[i];
+        if (!v) continue;
+        atomicAdd(&st0[khs + r.label[i]], v);
+        atomicAdd(&st1[khs + r.label[i]], v);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rehist(BatchArgs b, ImageDesc one,
+                                                     const uint8_t *rgb_one, int64_t pitch_one,
+                                                     const int2 *map,
+                                                     const uint8_t *const *rgb_table,
+                                                     const int64_t *pitch_table) {
+    __shared__ RehistLds r;
+    const int lg = xcd_group();
+    if (b.nimg == 1) {
+        rehist_tile(one.d, rgb_one, pitch_one, b.ar.bins, b.ar.lab, b.ar.state[0],
+                    b.ar.state[1], lg, r);
+        return;
+    }
+    const int2 e = map[lg];
+    const ImageDesc g = b.imgs[e.x];
+    rehist_tile(g.d, rgb_table[e.x], pitch_table[e.x], b.ar.bins + g.bins, b.ar.lab + g.lab,
+                b.ar.state[0] + g.state, b.ar.state[1] + g.state, e.y, r);
+}
+
+// ---------------------------------------------------------------------------
 // Pixel labels of one image from a block grid of a level (output of a state
 // stopped at a block level).
 // One workgroup per (row, chunk of kThreads columns).
@@ -152,6 +280,14 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
                        const int64_t *pitch_table, int groups, hipStream_t s) {
     hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one, map,
                        rgb_table, pitch_table);
+    return hipGetLastError();
+}
+
+hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
+                         int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
+                         const int64_t *pitch_table, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(k_rehist, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one,
+                       map, rgb_table, pitch_table);
     return hipGetLastError();
 }
 

@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
                                   ctypes.POINTER(seeds_params), P], S),
             "seeds_batch_reinit": ([P, ctypes.POINTER(P), ctypes.POINTER(I64), P], S),
             "seeds_batch_count": ([P], I32),
+            "seeds_warm_start": ([P, P, I64, P], S),
+            "seeds_batch_warm_start": ([P, ctypes.POINTER(P), ctypes.POINTER(I64), P], S),
             "seeds_batch_labels": ([P, I32, P, I32, P], S),
             "seeds_batch_histograms": ([P, I32, P, P, I32, P], S),
             "seeds_batch_num_superpixels": ([P, I32], I32),
@@ -157,17 +159,34 @@ def seeds_batch_init(images, num_superpixels, params: seeds_params, levels=None,
     return ctx
 
 
-def seeds_batch_reinit(ctx, images, stream=None) -> None:
+def _image_tables(ctx, images):
     n = len(images)
+    if n != seeds_batch_count(ctx):
+        raise ValueError(f"context holds {seeds_batch_count(ctx)} images, got {n}")
     ptrs = (ctypes.c_void_p * max(n, 1))()
     pitches = (ctypes.c_int64 * max(n, 1))()
     for i, rgb in enumerate(images):
         _check_rgb(rgb)
         ptrs[i] = rgb.data_ptr()
         pitches[i] = rgb.stride(0)
-    if n != seeds_batch_count(ctx):
-        raise ValueError(f"context holds {seeds_batch_count(ctx)} images, got {n}")
+    return ptrs, pitches
+
+
+def seeds_batch_reinit(ctx, images, stream=None) -> None:
+    ptrs, pitches = _image_tables(ctx, images)
     _check(lib().seeds_batch_reinit(ctx, ptrs, pitches, _stream(stream)))
+
+
+def seeds_warm_start(ctx, rgb: torch.Tensor, stream=None) -> None:
+    """Next frame of a stream: keep the labels, re-bin, recount; the next
+    seeds_refine runs I pixel sweeps."""
+    _check_rgb(rgb)
+    _check(lib().seeds_warm_start(ctx, rgb.data_ptr(), rgb.stride(0), _stream(stream)))
+
+
+def seeds_batch_warm_start(ctx, images, stream=None) -> None:
+    ptrs, pitches = _image_tables(ctx, images)
+    _check(lib().seeds_batch_warm_start(ctx, ptrs, pitches, _stream(stream)))
 
 
 def seeds_batch_count(ctx) -> int:

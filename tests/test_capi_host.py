@@ -168,6 +168,8 @@ def test_batch_null_arguments(S):
     assert L.seeds_batch_histograms(None, 0, None, None, 0, None) == S.SEEDS_E_INVAL
     assert L.seeds_batch_num_superpixels(None, 0) == -1
     assert L.seeds_batch_count(None) == -1
+    assert L.seeds_warm_start(None, None, 0, None) == S.SEEDS_E_INVAL
+    assert L.seeds_batch_warm_start(None, None, None, None) == S.SEEDS_E_INVAL
 
 
 def test_batch_init_without_a_device_reports_device_error(S):
