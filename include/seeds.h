@@ -233,6 +233,36 @@ seeds_status seeds_batch_histograms(const seeds_ctx *ctx, int32_t image, int32_t
                                     int32_t *size, int32_t out_is_host, void *hip_stream);
 int32_t seeds_batch_num_superpixels(const seeds_ctx *ctx, int32_t image);
 
+/* ---- Quality metrics -----------------------------------------------------
+ * UE, CUE, ASA and BR of Sec. 6.1 for a segmentation s against a ground
+ * truth g, as exact integer numerators:
+ *   UE  = ue / pixels,  ue  = sum_i sum_{k: s_k meets g_i} |s_k - g_i|  (eq. ue)
+ *   ASA = asa / pixels, asa = sum_k max_i |s_k & g_i|
+ *   CUE = cue / pixels, cue = sum_k |s_k - g_max(s_k)| (= pixels - asa)
+ *   BR  = br_hits / br_total: ground-truth boundary pixels with a boundary
+ *         pixel of s at Euclidean distance < eps, over all ground-truth
+ *         boundary pixels. A pixel is a boundary pixel of a segmentation when
+ *         one of its in-image 4-neighbours carries another segment.        */
+typedef struct {
+    int64_t pixels;
+    int64_t ue;
+    int64_t asa;
+    int64_t cue;
+    int64_t br_hits;
+    int64_t br_total;
+} seeds_quality;
+
+/* labels, truth: device pointers to H x W int32, row-major, with values in
+ * [0, num_labels) and [0, num_truth). eps in [1, 64] (the paper uses 2).
+ * num_labels * num_truth <= 2^28 (the overlap table). The call allocates the
+ * table in stream order, waits for the stream and writes *out (host).
+ * Out-of-range values are detected on the device: the call then returns
+ * SEEDS_E_INVAL after the device work (every other SEEDS_E_INVAL comes
+ * before it).                                                              */
+seeds_status seeds_quality_metrics(const int32_t *labels, const int32_t *truth, int32_t H,
+                                   int32_t W, int32_t num_labels, int32_t num_truth, int32_t eps,
+                                   seeds_quality *out, void *hip_stream);
+
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */
 seeds_status seeds_destroy(seeds_ctx *ctx);

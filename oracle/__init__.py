@@ -79,6 +79,8 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_energy.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.oracle_seeds.argtypes = [P, I32, I32, I64, I32, I32, I32, I32, I32, I32, I32, P, P, P]
     L.oracle_seeds.restype = I32
+    L.oracle_quality.argtypes = [P, P, I32, I32, I32, I32, I32, P]
+    L.oracle_quality.restype = I32
     return L
 
 
@@ -238,3 +240,17 @@ def seeds(rgb: np.ndarray, K: int, levels: int, bins: int = 5, iters: int = 4, g
     if k < 0:
         raise ValueError("oracle refused the parameters")
     return labels, hist, size
+
+
+def quality(labels: np.ndarray, truth: np.ndarray, K: int, R: int, eps: int = 2,
+            cdll: ctypes.CDLL | None = None) -> dict:
+    """Quality metrics of Sec. 6.1 as integer numerators (see oracle_quality):
+    keys N, ue, asa, cue, br_hits, br_total."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    gt = np.ascontiguousarray(truth, dtype=np.int32)
+    assert lab.shape == gt.shape and lab.ndim == 2
+    out = np.zeros(6, np.int64)
+    L = cdll or lib()
+    if L.oracle_quality(_ptr(lab), _ptr(gt), lab.shape[0], lab.shape[1], K, R, eps, _ptr(out)) != 0:
+        raise ValueError("label or segment out of range")
+    return dict(zip(["N", "ue", "asa", "cue", "br_hits", "br_total"], (int(v) for v in out)))

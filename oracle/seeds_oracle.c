@@ -650,3 +650,70 @@ int oracle_seeds(const uint8_t *rgb, int H, int W, int64_t pitch, int K, int L, 
     oracle_free(st);
     return k;
 }
+
+/* ------------------------------------------------------------------ */
+/* Quality metrics of a segmentation s (labels in [0,K)) against ground
+ * truth g (segments in [0,R)), as defined in Sec. 6.1. Returned as integer
+ * numerators over N = H*W (UE, CUE, ASA) and over |B(g)| (BR):
+ *   out[0] N
+ *   out[1] UE numerator   sum_i sum_{k: s_k meets g_i} |s_k - g_i|     (eq. ue)
+ *   out[2] ASA numerator  sum_k max_i |s_k & g_i|
+ *   out[3] CUE numerator  sum_k |s_k - g_max(s_k)|, g_max the segment of
+ *                         largest overlap (ties: the smaller index)
+ *   out[4] BR hits        pixels p of B(g) with some q of B(s), |p-q| < eps
+ *   out[5] |B(g)|
+ * Reading: a pixel lies on the boundary B(.) of a segmentation when one of
+ * its in-image 4-neighbours carries another segment; distances are
+ * Euclidean between pixel positions. Returns -1 on an out-of-range value. */
+static int on_boundary(const int32_t *seg, int H, int W, int x, int y) {
+    const int32_t v = seg[(int64_t)y * W + x];
+    if (x > 0 && seg[(int64_t)y * W + x - 1] != v) return 1;
+    if (x + 1 < W && seg[(int64_t)y * W + x + 1] != v) return 1;
+    if (y > 0 && seg[(int64_t)(y - 1) * W + x] != v) return 1;
+    if (y + 1 < H && seg[(int64_t)(y + 1) * W + x] != v) return 1;
+    return 0;
+}
+
+int oracle_quality(const int32_t *labels, const int32_t *truth, int H, int W, int K, int R,
+                   int eps, int64_t *out) {
+    const int64_t N = (int64_t)H * W;
+    for (int64_t p = 0; p < N; ++p)
+        if (labels[p] < 0 || labels[p] >= K || truth[p] < 0 || truth[p] >= R) return -1;
+    /* overlaps |s_k & g_i| and sizes |s_k| */
+    int64_t *ov = (int64_t *)calloc((size_t)K * R, sizeof(int64_t));
+    int64_t *sk = (int64_t *)calloc((size_t)K, sizeof(int64_t));
+    for (int64_t p = 0; p < N; ++p) {
+        ov[(int64_t)labels[p] * R + truth[p]] += 1;
+        sk[labels[p]] += 1;
+    }
+    int64_t ue = 0, asa = 0, cue = 0;
+    for (int i = 0; i < R; ++i)
+        for (int k = 0; k < K; ++k)
+            if (ov[(int64_t)k * R + i] > 0) ue += sk[k] - ov[(int64_t)k * R + i];
+    for (int k = 0; k < K; ++k) {
+        int best = 0;
+        for (int i = 1; i < R; ++i)
+            if (ov[(int64_t)k * R + i] > ov[(int64_t)k * R + best]) best = i;
+        asa += ov[(int64_t)k * R + best];
+        cue += sk[k] - ov[(int64_t)k * R + best];
+    }
+    /* boundary recall */
+    int64_t hits = 0, total = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            if (!on_boundary(truth, H, W, x, y)) continue;
+            total++;
+            int found = 0;
+            for (int dy = -eps; dy <= eps && !found; ++dy)
+                for (int dx = -eps; dx <= eps && !found; ++dx) {
+                    if (dx * dx + dy * dy >= eps * eps) continue;
+                    const int qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qy < 0 || qx >= W || qy >= H) continue;
+                    found = on_boundary(labels, H, W, qx, qy);
+                }
+            hits += found;
+        }
+    out[0] = N; out[1] = ue; out[2] = asa; out[3] = cue; out[4] = hits; out[5] = total;
+    free(ov); free(sk);
+    return 0;
+}

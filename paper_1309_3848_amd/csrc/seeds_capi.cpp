@@ -853,6 +853,40 @@ seeds_status seeds_destroy(seeds_ctx *ctx) {
     return SEEDS_OK;
 }
 
+seeds_status seeds_quality_metrics(const int32_t *labels, const int32_t *truth, int32_t H,
+                                   int32_t W, int32_t num_labels, int32_t num_truth, int32_t eps,
+                                   seeds_quality *out, void *hip_stream) {
+    if (!labels || !truth || !out) return fail(SEEDS_E_INVAL, "NULL pointer");
+    if (H < 1 || W < 1 || (int64_t)H * W >= ((int64_t)1 << 31))
+        return fail(SEEDS_E_INVAL, "image size %d x %d outside [1, 2^31) pixels", W, H);
+    if (num_labels < 1 || num_truth < 1 ||
+        (int64_t)num_labels * num_truth > ((int64_t)1 << 28))
+        return fail(SEEDS_E_INVAL, "%d labels x %d segments: need both >= 1 and product <= 2^28",
+                    num_labels, num_truth);
+    if (eps < 1 || eps > 64) return fail(SEEDS_E_INVAL, "eps %d outside [1,64]", eps);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t table_bytes = align_up((size_t)num_labels * num_truth * 4);
+    void *mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, table_bytes + 64, s);
+    if (e != hipSuccess) return fail(SEEDS_E_NOMEM, "hipMallocAsync: %s", hipGetErrorString(e));
+    unsigned long long cnt[6] = {0, 0, 0, 0, 0, 0};
+    auto *d_cnt = (unsigned long long *)((char *)mem + table_bytes);
+    e = launch_quality(labels, truth, H, W, num_labels, num_truth, eps, (int32_t *)mem, d_cnt, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipFreeAsync(mem, s);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(SEEDS_E_DEVICE, "quality metrics: %s", hipGetErrorString(e));
+    if (cnt[5]) return fail(SEEDS_E_INVAL, "%llu label or segment values out of range", cnt[5]);
+    out->pixels = (int64_t)H * W;
+    out->ue = (int64_t)cnt[0];
+    out->asa = (int64_t)cnt[1];
+    out->cue = (int64_t)cnt[2];
+    out->br_hits = (int64_t)cnt[3];
+    out->br_total = (int64_t)cnt[4];
+    return SEEDS_OK;
+}
+
 const char *seeds_last_error(void) { return g_err; }
 
 }  // extern "C"

@@ -192,6 +192,12 @@ hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t
 hipError_t launch_expand(const Dims &d, const int32_t *units, int level, int32_t *out,
                          hipStream_t s);
 
+// Quality metrics (overlap table of K x R int32 and six 64-bit counters,
+// both zeroed here): UE, ASA and CUE numerators, BR hits, |B(g)|, and the
+// number of out-of-range values.
+hipError_t launch_quality(const int32_t *lab, const int32_t *gt, int H, int W, int K, int R,
+                          int eps, int32_t *table, unsigned long long *cnt, hipStream_t s);
+
 // Persistent cooperative refinement of a single image.
 hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,
                          const Sched &start, int max_phases, uint32_t stamp, hipStream_t s);

@@ -41,6 +41,10 @@ class seeds_params(ctypes.Structure):
 SEEDS_MAX_BATCH = 4096
 
 
+class seeds_quality(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("pixels", "ue", "asa", "cue", "br_hits", "br_total")]
+
+
 class seeds_image(ctypes.Structure):
     _fields_ = [("rgb", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("row_pitch_bytes", ctypes.c_int64), ("num_superpixels", ctypes.c_int32),
@@ -80,6 +84,8 @@ def lib() -> ctypes.CDLL:
             "seeds_batch_labels": ([P, I32, P, I32, P], S),
             "seeds_batch_histograms": ([P, I32, P, P, I32, P], S),
             "seeds_batch_num_superpixels": ([P, I32], I32),
+            "seeds_quality_metrics": ([P, P, I32, I32, I32, I32, I32, ctypes.POINTER(seeds_quality),
+                                       P], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -270,6 +276,23 @@ def seeds_sync(ctx, stream=None) -> None:
 
 def seeds_destroy(ctx) -> None:
     _check(lib().seeds_destroy(ctx))
+
+
+def seeds_quality_metrics(labels: torch.Tensor, truth: torch.Tensor, num_labels: int,
+                          num_truth: int, eps: int = 2, stream=None) -> dict:
+    """UE, CUE, ASA and BR numerators (Sec. 6.1) of device int32 label maps;
+    keys N, ue, asa, cue, br_hits, br_total."""
+    for t in (labels, truth):
+        if t.dtype != torch.int32 or t.dim() != 2 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("labels and truth must be contiguous H x W int32 device tensors")
+    if labels.shape != truth.shape:
+        raise ValueError("labels and truth differ in shape")
+    q = seeds_quality()
+    H, W = labels.shape
+    _check(lib().seeds_quality_metrics(labels.data_ptr(), truth.data_ptr(), H, W, num_labels,
+                                       num_truth, eps, ctypes.byref(q), _stream(stream)))
+    return dict(N=q.pixels, ue=q.ue, asa=q.asa, cue=q.cue, br_hits=q.br_hits,
+                br_total=q.br_total)
 
 
 def seeds_last_error() -> str:

@@ -182,3 +182,18 @@ def test_batch_init_without_a_device_reports_device_error(S):
     st = S.lib().seeds_batch_init(ctypes.byref(ctx), arr, 2, ctypes.byref(p), None)
     assert st in (S.SEEDS_E_DEVICE, S.SEEDS_E_NOMEM)
     assert not ctx.value
+
+
+def test_quality_metrics_argument_checks(S):
+    L = S.lib()
+    q = S.seeds_quality()
+    d = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert L.seeds_quality_metrics(None, d, 4, 4, 2, 2, 2, ctypes.byref(q), None) == S.SEEDS_E_INVAL
+    assert L.seeds_quality_metrics(d, d, 4, 4, 2, 2, 2, None, None) == S.SEEDS_E_INVAL
+    assert L.seeds_quality_metrics(d, d, 0, 4, 2, 2, 2, ctypes.byref(q), None) == S.SEEDS_E_INVAL
+    assert L.seeds_quality_metrics(d, d, 4, 4, 0, 2, 2, ctypes.byref(q), None) == S.SEEDS_E_INVAL
+    assert L.seeds_quality_metrics(d, d, 4, 4, 1 << 15, 1 << 14, 2, ctypes.byref(q),
+                                   None) == S.SEEDS_E_INVAL
+    assert "2^28" in S.seeds_last_error()
+    assert L.seeds_quality_metrics(d, d, 4, 4, 2, 2, 0, ctypes.byref(q), None) == S.SEEDS_E_INVAL
+    assert L.seeds_quality_metrics(d, d, 4, 4, 2, 2, 65, ctypes.byref(q), None) == S.SEEDS_E_INVAL
