@@ -18,6 +18,11 @@ labels (re-binned, recounted, 4 pixel sweeps); K = 5000, 4 levels, 5 bins.
 Every frame is resident in HBM before timing; value is frames x pixels over
 the wall time of the pass, latency is per frame.
 
+`--workload quality` refines 20 481 x 321 images (K = 200) three ways - the
+initial grid, pixel-level updates only (one level), SEEDS with 3 levels - and
+reports the metrics of Sec. 6.1 (UE, CUE, ASA, BR with eps 2) against the
+images' Voronoi region maps, computed on the device.
+
 `--workload batch64` measures the mixed batch instead: 64 synthetic images,
 W ~ U{320..1920}, H ~ U{240..1080}, 50-600 Voronoi regions, noise sigma in
 [4,16], K ~ U{200..2000} clamped to N/256, 3-4 levels, 5 bins, 4 sweeps,
@@ -219,18 +224,24 @@ def run_batch(args) -> int:
     if not args.no_cpu_baseline:
         import oracle
         order = np.argsort([s["H"] * s["W"] for s in specs])
+        # the smallest, median and largest image first, then others in turn
+        # until about cpu_seconds of oracle work
         sample = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+        sample += [i for i in range(len(specs)) if i not in sample]
         t2 = time.perf_counter()
-        px, same = 0, True
+        px, same, used = 0, True, []
         for i in sample:
+            if len(used) >= 3 and time.perf_counter() - t2 >= args.cpu_seconds:
+                break
             ref, _, _ = oracle.seeds(imgs[i], Ks[i], Ls[i], BINS, ITERS, GAMMA, RULE)
             px += imgs[i].shape[0] * imgs[i].shape[1]
             same &= bool(np.array_equal(gpu_labels[i], ref))
+            used.append(i)
         cpu_s = time.perf_counter() - t2
         result["cpu_baseline"] = {
             "value": round(px / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"images {sample} of the batch (smallest, median, largest), full runs, "
-                      f"single-threaded C oracle, {cpu_s:.1f} s"}
+            "sample": f"{len(used)} images of the batch ({px / 1e6:.1f} Mpx; first the smallest, "
+                      f"median and largest), full runs, single-threaded C oracle, {cpu_s:.1f} s"}
         result["bitexact_vs_oracle"] = same
     print(json.dumps(result), flush=True)
     return 0
@@ -368,10 +379,112 @@ def run_stream(args) -> int:
     return 0
 
 
+def run_quality(args) -> int:
+    import numpy as np
+    import torch
+
+    from paper_1309_3848_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build(force=True)
+    from paper_1309_3848_amd import seeds as S
+    from paper_1309_3848_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    QH, QW, QK, QR, n = 321, 481, 200, 30, 20
+    pairs = [synth.voronoi_image(QH, QW, QR, 8.0, sd, return_regions=True) for sd in range(1, n + 1)]
+    rgbs = [torch.from_numpy(im).to(dev) for im, _ in pairs]
+    truths = [torch.from_numpy(reg).to(dev) for _, reg in pairs]
+    stream = torch.cuda.current_stream()
+    outs = [torch.empty((QH, QW), dtype=torch.int32, device=dev) for _ in range(n)]
+    methods = {"grid": (3, 0), "sph": (1, -1), "seeds": (3, -1)}   # (levels, phases)
+    quality, labels_of, timing, keff_of = {}, {}, {}, {}
+    for name, (L, phases) in methods.items():
+        ctx = S.seeds_batch_init(rgbs, QK, S.make_params(L, BINS, ITERS, GAMMA, RULE),
+                                 levels=L, stream=stream)
+
+        def step():
+            S.seeds_batch_reinit(ctx, rgbs, stream)
+            if phases < 0:
+                S.seeds_refine(ctx, stream)
+            for i in range(n):
+                S.seeds_batch_labels(ctx, i, outs[i], stream)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        timing[name] = e0.elapsed_time(e1) / args.steps
+        keff = keff_of[name] = S.seeds_batch_num_superpixels(ctx, 0)
+        S.seeds_destroy(ctx)
+        qs = [S.seeds_quality_metrics(outs[i], truths[i], keff, QR, 2, stream) for i in range(n)]
+        labels_of[name] = [o.cpu().numpy() for o in outs]
+        quality[name] = {
+            "UE": round(float(np.mean([q["ue"] / q["N"] for q in qs])), 5),
+            "CUE": round(float(np.mean([q["cue"] / q["N"] for q in qs])), 5),
+            "ASA": round(float(np.mean([q["asa"] / q["N"] for q in qs])), 5),
+            "BR_eps2": round(float(np.mean([q["br_hits"] / q["br_total"] for q in qs])), 5),
+        }
+    # the metric kernels themselves, on the SEEDS labels
+    lab_dev = [torch.from_numpy(l).to(dev) for l in labels_of["seeds"]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        for i in range(n):
+            S.seeds_quality_metrics(lab_dev[i], truths[i], keff_of["seeds"], QR, 2, stream)
+    metric_ms = (time.perf_counter() - t0) * 1e3 / (reps * n)
+    npx = QH * QW * n
+    result = {
+        "metric": METRIC, "value": round(npx / (timing["seeds"] * 1e-3) / 1e6, 2),
+        "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(timing["seeds"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{n} images 481x321 RGB u8 (30 Voronoi regions, noise sigma 8, "
+                               "seeds 1-20) with their Voronoi region maps as ground truth; "
+                               "K=200, 5 bins, 4 sweeps, gamma 1, Prop. 1 rule; one batch context "
+                               "per method; metrics of Sec. 6.1 on the device (BR with eps 2)",
+                   "methods": {"grid": "initial grid, no refinement (3 levels)",
+                               "sph": "pixel-level updates only (1 level)",
+                               "seeds": "3 levels (block sides 4, 2, then pixels)"},
+                   "step": "batch reinit + refine + labels of 20 images (device)"},
+        "quality": quality,
+        "ms_per_batch": {k: round(v, 4) for k, v in timing.items()},
+        "metric_call_ms": round(metric_ms, 4),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t2 = time.perf_counter()
+        same, done = True, 0
+        while done < n and (done < 3 or time.perf_counter() - t2 < args.cpu_seconds):
+            i = done
+            ref, _, _ = oracle.seeds(pairs[i][0], QK, 3, BINS, ITERS, GAMMA, RULE)
+            same &= bool(np.array_equal(ref, labels_of["seeds"][i]))
+            q_cpu = oracle.quality(ref, pairs[i][1], keff_of["seeds"], QR, 2)
+            q_gpu = S.seeds_quality_metrics(lab_dev[i], truths[i], keff_of["seeds"], QR, 2, stream)
+            same &= q_cpu == q_gpu
+            done += 1
+        cpu_s = time.perf_counter() - t2
+        result["cpu_baseline"] = {
+            "value": round(done * QH * QW / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"images 1-{done}: full oracle runs (3 levels) and oracle metrics, "
+                      f"single-threaded C oracle, {cpu_s:.1f} s"}
+        result["bitexact_vs_oracle"] = same
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single1080p", "batch64", "stream4k"],
+    ap.add_argument("--workload", choices=["single1080p", "batch64", "stream4k", "quality"],
                     default="single1080p")
     ap.add_argument("--frames", type=int, default=300, help="stream4k: frames of the stream")
     ap.add_argument("--steps", type=int, default=None)
@@ -386,6 +499,10 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(images are independent: several GPUs would each refine their own images)", file=sys.stderr)
         return 2
+    if args.workload == "quality":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 3 if args.warmup is None else args.warmup
+        return run_quality(args)
     if args.workload == "stream4k":
         args.warmup = 3 if args.warmup is None else args.warmup
         return run_stream(args)

@@ -56,6 +56,8 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_free.argtypes = [P]
     L.oracle_set_pixel_labels.argtypes = [P, P]
     L.oracle_set_pixel_labels.restype = I32
+    L.oracle_next_phase.argtypes = [P]
+    L.oracle_next_phase.restype = I32
     L.oracle_warm_start.argtypes = [P, P, ctypes.c_int64]
     L.oracle_warm_start.restype = I32
     L.oracle_set_unit_labels.argtypes = [P, I32, P]
@@ -151,6 +153,10 @@ class Oracle:
 
     def phase(self, cls: int) -> int:
         return self._L.oracle_phase(self._h, cls)
+
+    def next_phase(self) -> int:
+        """Class of the next phase (state brought to its level), or -1."""
+        return self._L.oracle_next_phase(self._h)
 
     def decide(self, cls: int):
         n = self._L.oracle_decide_class(self._h, cls, None, 0)

@@ -527,6 +527,19 @@ int oracle_run(oracle_state *st, int max_phases) {
     return done;
 }
 
+/* Class of the next phase of the schedule, with the state brought to that
+ * phase's level as oracle_run would before executing it; -1 when no phase
+ * of the current schedule is left. Lets a caller inspect the decisions of
+ * every phase (oracle_decide_class) before running it (oracle_run(st, 1)). */
+int oracle_next_phase(oracle_state *st) {
+    while (st->cur_level >= 0 && st->cur_sweep >= st->I) {
+        st->cur_level--; st->cur_sweep = 0; st->cur_class = 0;
+    }
+    if (st->cur_level < 0) return -1;
+    while (st->level > st->cur_level) descend(st);
+    return st->cur_class;
+}
+
 /* Sequential variant: same levels and sweeps, units in raster order, every
  * decision sees all earlier moves, no classes and no drop rule.          */
 void oracle_run_sequential(oracle_state *st) {
