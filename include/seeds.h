@@ -233,6 +233,75 @@ seeds_status seeds_batch_histograms(const seeds_ctx *ctx, int32_t image, int32_t
                                     int32_t *size, int32_t out_is_host, void *hip_stream);
 int32_t seeds_batch_num_superpixels(const seeds_ctx *ctx, int32_t image);
 
+/* ---- Serving -------------------------------------------------------------
+ * A request loop with continuous batching. Requests (images on the device)
+ * are submitted at any time; each seeds_server_step enqueues one tick on the
+ * server's stream: the images admitted in this tick are initialised, every
+ * image in flight advances by one phase of its own schedule (levels L-1 .. 0,
+ * I sweeps of nine classes; an image joins at its top level while others are
+ * in the middle of theirs), and the labels of images whose schedule ended are
+ * written to their outputs. Requests are admitted in arrival order while the
+ * device memory budget (pixels, histograms, move logs) and max_inflight
+ * allow; an image's memory returns to the pool two ticks after its last
+ * phase. Every result equals that of a single-image context with the same
+ * parameters, bit for bit. Only the Prop. 1 block rule is served.          */
+typedef struct seeds_server seeds_server;
+
+typedef struct {
+    int32_t bins_per_channel; /* B in [1,6]                                        */
+    int32_t iters_per_level;  /* I >= 1                                            */
+    int32_t gamma;            /* boundary-term weight, [0,65536]                  */
+    int32_t max_levels;       /* largest L of any request, [1,8]                  */
+    int64_t hbm_budget_bytes; /* device memory of the server, [64 MiB, 128 GiB]:
+                                 60% pixels (7 B per pixel), 8% histograms, 32%
+                                 move logs                                         */
+    int32_t max_inflight;     /* most images refined together, [1,65536]          */
+} seeds_server_params;
+
+typedef struct {
+    int64_t submitted, admitted, completed, ticks;
+    int64_t queued, inflight, peak_inflight;
+    int64_t bytes_in_use, peak_bytes_in_use, budget_bytes; /* pixels + histograms */
+} seeds_server_stats;
+
+/* B = 5, I = 4, gamma = 1, max_levels = 4, 4 GiB, 512 images.              */
+seeds_status seeds_server_default_params(seeds_server_params *p);
+
+/* Create a server whose ticks run on hip_stream; allocates the budget once.  */
+seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *p,
+                                 void *hip_stream);
+
+/* Queue one request: an H x W image as for seeds_init (device pointer, kept
+ * alive until its labels are reported), num_superpixels and levels
+ * (<= max_levels), and where its H x W int32 labels go (out_is_host = 1:
+ * host memory, which should be pinned so the copy stays asynchronous).
+ * SEEDS_E_INVAL for bad arguments or an image that cannot fit the budget.
+ * *request_id (may be NULL) identifies it in seeds_server_poll.             */
+seeds_status seeds_server_submit(seeds_server *s, const uint8_t *rgb, int32_t H, int32_t W,
+                                 int64_t row_pitch_bytes, int32_t num_superpixels,
+                                 int32_t levels, int32_t *labels_out, int32_t out_is_host,
+                                 int64_t *request_id);
+
+/* Enqueue one tick (admission, initialisation, level transitions, one phase
+ * of every image in flight, label outputs). The host may run up to 8 ticks
+ * ahead of the device; the call waits when it is that far ahead.
+ * *pending (may be NULL) receives the requests not yet finished on the host
+ * side (queued, in flight, or waiting for their memory to return).          */
+seeds_status seeds_server_step(seeds_server *s, int32_t *pending);
+
+/* Report requests whose labels have been written (device work complete):
+ * up to max_ids ids into done_ids, their number in *n_done. Each request is
+ * reported once.                                                             */
+seeds_status seeds_server_poll(seeds_server *s, int64_t *done_ids, int32_t max_ids,
+                               int32_t *n_done);
+
+/* Counters of the server (host-side bookkeeping).                            */
+seeds_status seeds_server_get_stats(const seeds_server *s, seeds_server_stats *out);
+
+/* Wait for the stream, then release the server and every request. NULL is
+ * accepted.                                                                  */
+seeds_status seeds_server_destroy(seeds_server *s);
+
 /* ---- Quality metrics -----------------------------------------------------
  * UE, CUE, ASA and BR of Sec. 6.1 for a segmentation s against a ground
  * truth g, as exact integer numerators:

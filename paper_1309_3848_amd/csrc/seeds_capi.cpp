@@ -24,9 +24,22 @@
 
 using namespace seeds;
 
-namespace {
+namespace seeds {
 
+// Text of the last failure on this thread (seeds_last_error).
 thread_local char g_err[512] = "";
+
+seeds_status set_error(seeds_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+}  // namespace seeds
+
+namespace {
 
 seeds_status fail(seeds_status st, const char *fmt, ...) {
     va_list ap;

@@ -15,6 +15,10 @@
 
 namespace seeds {
 
+// Record the text of a failure for seeds_last_error() on this thread and
+// return st.
+seeds_status set_error(seeds_status st, const char *fmt, ...);
+
 // Histogram rows are padded so every row starts on a 32-byte boundary.
 __host__ __device__ inline int hist_stride(int nbins) { return (nbins + 7) & ~7; }
 
@@ -102,6 +106,17 @@ struct Arenas {
     int2 *log;          // per-workgroup delta logs: [2 parities][log_groups][log_cap]
     int32_t *log_n;     // entries in each log: [2][log_groups]
     uint32_t *sync;     // persistent kernel: barrier count, generation, error flag
+};
+
+// One image's share of a mixed launch (the serving engine): its descriptor,
+// what it does in the launch and which logical workgroups do it. Items of a
+// launch are sorted by `first` and none is empty.
+struct TickItem {
+    ImageDesc g;
+    const uint8_t *rgb;  // init items: the image's pixels
+    int64_t pitch;
+    int level, cls;      // phase items: the phase; descend items: the level left
+    int first, groups;   // logical workgroups [first, first + groups)
 };
 
 // Device view of a whole context for one launch.
@@ -197,6 +212,27 @@ hipError_t launch_expand(const Dims &d, const int32_t *units, int level, int32_t
 // number of out-of-range values.
 hipError_t launch_quality(const int32_t *lab, const int32_t *gt, int H, int W, int K, int R,
                           int eps, int32_t *table, unsigned long long *cnt, hipStream_t s);
+
+// Mixed launches of the serving engine: every item is one image. Phase items
+// run their own (level, class) with the Prop. 1 rule; `max_level` is the
+// largest level among them; replay as in launch_phase.
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickItem *items, int nitems,
+                              int max_level, int par, int groups, int replay_groups,
+                              hipStream_t s);
+hipError_t launch_descend_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                                hipStream_t s);
+// Zero both state copies of every item's image, then initialise it (quantise,
+// grid, histograms) from item.rgb.
+hipError_t launch_zero_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                             hipStream_t s);
+hipError_t launch_init_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                             hipStream_t s);
+// Workgroups of one image's state-zeroing share.
+constexpr int kZeroPerGroup = 4096;
+__host__ __device__ inline int zero_groups(const Dims &d) {
+    const int64_t n = (int64_t)d.K * d.hs + d.K;
+    return (int)((n + kZeroPerGroup - 1) / kZeroPerGroup);
+}
 
 // Persistent cooperative refinement of a single image.
 hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,

@@ -124,6 +124,40 @@ __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
     init_image(b, b.imgs[e.x], rgb_table[e.x], pitch_table[e.x], e.y, sl);
 }
 
+// Serving engine: items of newly admitted images. Their state regions are
+// zeroed by one launch (both copies), then initialised by the next.
+__device__ __forceinline__ int find_init_item(const TickItem *items, int n, int lg) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first <= lg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_mixed(BatchArgs b, const TickItem *items,
+                                                         int nitems) {
+    const int lg = xcd_group();
+    const TickItem &it = items[find_init_item(items, nitems, lg)];
+    const int64_t n = (int64_t)it.g.d.K * it.g.d.hs + it.g.d.K;
+    const int64_t lo = (int64_t)(lg - it.first) * kZeroPerGroup;
+    const int64_t hi = min(n, lo + kZeroPerGroup);
+    int32_t *s0 = b.ar.state[0] + it.g.state, *s1 = b.ar.state[1] + it.g.state;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+        s0[i] = 0;
+        s1[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_mixed(BatchArgs b, const TickItem *items,
+                                                         int nitems) {
+    __shared__ InitSlots sl;
+    const int lg = xcd_group();
+    const TickItem &it = items[find_init_item(items, nitems, lg)];
+    init_image(b, it.g, it.rgb, it.pitch, lg - it.first, sl);
+}
+
 // ---------------------------------------------------------------------------
 // Warm start on a new frame: bins of every pixel from the new frame (Sec.
 // 4.1) and the colour histograms and sizes of the superpixels from the labels
@@ -280,6 +314,18 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
                        const int64_t *pitch_table, int groups, hipStream_t s) {
     hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one, map,
                        rgb_table, pitch_table);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_mixed, dim3(groups), dim3(kThreads), 0, s, b, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_init_mixed, dim3(groups), dim3(kThreads), 0, s, b, items, nitems);
     return hipGetLastError();
 }
 

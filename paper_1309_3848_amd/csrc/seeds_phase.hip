@@ -25,10 +25,17 @@ __device__ __forceinline__ ImageView resolve(const BatchArgs &b, const ImageDesc
     }
 }
 
-template <bool BIG, bool BATCH>
-__global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const int2 *map,
-                                               int level, int cls, int par, int pass,
-                                               uint32_t stamp, int replay_groups) {
+// Work of one workgroup in a phase launch: its image view and the phase.
+struct PhaseWork {
+    ImageView v;
+    int level, cls;
+};
+
+// The body shared by every phase launch. `find` yields the workgroup's work;
+// it runs after the replay prefetch is issued so that the two overlap.
+template <bool BIG, typename Find>
+__device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
+                                           uint32_t stamp, int replay_groups) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
     __shared__ PixelList pl;
@@ -49,12 +56,12 @@ __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const
         pre_n = b.ar.log_n[own_slot];
         if (threadIdx.x < kPre) pre = b.ar.log[own_slot * b.log_cap + threadIdx.x];
     }
-    const ImageView v = resolve<BATCH>(b, one, map, level, cls);
+    const PhaseWork w = find();
     int2 *mylog = b.ar.log + ((int64_t)par * b.log_groups + blockIdx.x) * b.log_cap;
-    if (level == 0)
-        pixel_phase(b, v, cls, par, t, mylog, pl);
+    if (w.level == 0)
+        pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
     else
-        block_phase_any<BIG>(b, v, level, cls, par, pass, stamp, sbin, t, mylog);
+        block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     if (replay_own) {
         const int n = min(pre_n, b.log_cap);
         if ((int)threadIdx.x < min(n, kPre)) atomicAdd(&W[pre.x], pre.y);
@@ -72,6 +79,49 @@ __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const
     table_flush(b, t, W, mylog);
     __syncthreads();
     if (threadIdx.x == 0) b.ar.log_n[(int64_t)par * b.log_groups + blockIdx.x] = min(t.n, b.log_cap);
+}
+
+template <bool BIG, bool BATCH>
+__global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const int2 *map,
+                                               int level, int cls, int par, int pass,
+                                               uint32_t stamp, int replay_groups) {
+    phase_body<BIG>(
+        b, [&]() { return PhaseWork{resolve<BATCH>(b, one, map, level, cls), level, cls}; }, par,
+        pass, stamp, replay_groups);
+}
+
+// Item of a mixed launch that holds logical workgroup lg: the last item whose
+// first workgroup is <= lg (items are sorted by `first`, none is empty).
+__device__ __forceinline__ int find_item(const TickItem *items, int n, int lg) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first <= lg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A mixed launch: every item is one image at its own phase (level, class).
+// Only the Prop. 1 rule (one pass per phase) runs this way.
+template <bool BIG>
+__global__ __launch_bounds__(kPT) void k_phase_mixed(BatchArgs b, const TickItem *items,
+                                                     int nitems, int par, int replay_groups) {
+    phase_body<BIG>(
+        b,
+        [&]() {
+            const int lg = xcd_group();
+            const TickItem &it = items[find_item(items, nitems, lg)];
+            return PhaseWork{make_view(b, it.g, lg - it.first, it.groups), it.level, it.cls};
+        },
+        par, 0, 0u, replay_groups);
+}
+
+__global__ __launch_bounds__(kPT) void k_descend_mixed(BatchArgs b, const TickItem *items,
+                                                       int nitems) {
+    const int lg = xcd_group();
+    const TickItem &it = items[find_item(items, nitems, lg)];
+    descend(make_view(b, it.g, lg - it.first, it.groups), it.level);
 }
 
 // After the last phase: add its deltas to the copy it read, so that both
@@ -117,6 +167,21 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
                              : (batch ? k_phase<false, true> : k_phase<false, false>);
     hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, one, map, level, cls, par, pass,
                        stamp, replay_groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickItem *items, int nitems,
+                              int max_level, int par, int groups, int replay_groups,
+                              hipStream_t s) {
+    const int lds = max_level == 0 ? 0 : kPT * seg_ppl(max_level);
+    auto fn = max_level >= 4 ? k_phase_mixed<true> : k_phase_mixed<false>;
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, items, nitems, par, replay_groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_descend_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_descend_mixed, dim3(groups), dim3(kPT), 0, s, b, items, nitems);
     return hipGetLastError();
 }
 

@@ -41,6 +41,18 @@ class seeds_params(ctypes.Structure):
 SEEDS_MAX_BATCH = 4096
 
 
+class seeds_server_params(ctypes.Structure):
+    _fields_ = [("bins_per_channel", ctypes.c_int32), ("iters_per_level", ctypes.c_int32),
+                ("gamma", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32)]
+
+
+class seeds_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "admitted", "completed", "ticks", "queued", "inflight", "peak_inflight",
+        "bytes_in_use", "peak_bytes_in_use", "budget_bytes")]
+
+
 class seeds_quality(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("pixels", "ue", "asa", "cue", "br_hits", "br_total")]
 
@@ -86,6 +98,14 @@ def lib() -> ctypes.CDLL:
             "seeds_batch_num_superpixels": ([P, I32], I32),
             "seeds_quality_metrics": ([P, P, I32, I32, I32, I32, I32, ctypes.POINTER(seeds_quality),
                                        P], S),
+            "seeds_server_default_params": ([ctypes.POINTER(seeds_server_params)], S),
+            "seeds_server_create": ([ctypes.POINTER(P), ctypes.POINTER(seeds_server_params), P], S),
+            "seeds_server_submit": ([P, P, I32, I32, I64, I32, I32, P, I32,
+                                     ctypes.POINTER(I64)], S),
+            "seeds_server_step": ([P, PI], S),
+            "seeds_server_poll": ([P, ctypes.POINTER(I64), I32, PI], S),
+            "seeds_server_get_stats": ([P, ctypes.POINTER(seeds_server_stats)], S),
+            "seeds_server_destroy": ([P], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -293,6 +313,55 @@ def seeds_quality_metrics(labels: torch.Tensor, truth: torch.Tensor, num_labels:
                                        num_truth, eps, ctypes.byref(q), _stream(stream)))
     return dict(N=q.pixels, ue=q.ue, asa=q.asa, cue=q.cue, br_hits=q.br_hits,
                 br_total=q.br_total)
+
+
+def seeds_server_default_params() -> seeds_server_params:
+    p = seeds_server_params()
+    _check(lib().seeds_server_default_params(ctypes.byref(p)))
+    return p
+
+
+def seeds_server_create(params: seeds_server_params, stream=None):
+    srv = ctypes.c_void_p()
+    _check(lib().seeds_server_create(ctypes.byref(srv), ctypes.byref(params), _stream(stream)))
+    return srv
+
+
+def seeds_server_submit(srv, rgb: torch.Tensor, num_superpixels: int, levels: int,
+                        out: torch.Tensor) -> int:
+    """Queue rgb (H x W x 3 uint8 device tensor); labels go to out (H x W int32,
+    device or pinned host tensor). Returns the request id."""
+    _check_rgb(rgb)
+    if out.dtype != torch.int32 or not out.is_contiguous() or tuple(out.shape) != tuple(rgb.shape[:2]):
+        raise ValueError("out must be a contiguous H x W int32 tensor")
+    rid = ctypes.c_int64()
+    _check(lib().seeds_server_submit(srv, rgb.data_ptr(), rgb.shape[0], rgb.shape[1],
+                                     rgb.stride(0), num_superpixels, levels, out.data_ptr(),
+                                     0 if out.is_cuda else 1, ctypes.byref(rid)))
+    return rid.value
+
+
+def seeds_server_step(srv) -> int:
+    pending = ctypes.c_int32()
+    _check(lib().seeds_server_step(srv, ctypes.byref(pending)))
+    return pending.value
+
+
+def seeds_server_poll(srv, max_ids: int = 1024) -> list:
+    ids = (ctypes.c_int64 * max_ids)()
+    n = ctypes.c_int32()
+    _check(lib().seeds_server_poll(srv, ids, max_ids, ctypes.byref(n)))
+    return [ids[i] for i in range(n.value)]
+
+
+def seeds_server_get_stats(srv) -> dict:
+    st = seeds_server_stats()
+    _check(lib().seeds_server_get_stats(srv, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in seeds_server_stats._fields_}
+
+
+def seeds_server_destroy(srv) -> None:
+    _check(lib().seeds_server_destroy(srv))
 
 
 def seeds_last_error() -> str:

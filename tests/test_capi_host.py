@@ -197,3 +197,32 @@ def test_quality_metrics_argument_checks(S):
     assert "2^28" in S.seeds_last_error()
     assert L.seeds_quality_metrics(d, d, 4, 4, 2, 2, 0, ctypes.byref(q), None) == S.SEEDS_E_INVAL
     assert L.seeds_quality_metrics(d, d, 4, 4, 2, 2, 65, ctypes.byref(q), None) == S.SEEDS_E_INVAL
+
+
+def test_server_argument_checks(S):
+    L = S.lib()
+    p = S.seeds_server_default_params()
+    assert (p.bins_per_channel, p.iters_per_level, p.gamma, p.max_levels) == (5, 4, 1, 4)
+    srv = ctypes.c_void_p()
+    for field, bad in (("bins_per_channel", 7), ("iters_per_level", 0), ("gamma", -1),
+                       ("max_levels", 9), ("max_inflight", 0), ("hbm_budget_bytes", 1 << 20)):
+        q = S.seeds_server_default_params()
+        setattr(q, field, bad)
+        assert L.seeds_server_create(ctypes.byref(srv), ctypes.byref(q), None) == S.SEEDS_E_INVAL
+        assert not srv.value
+    assert L.seeds_server_create(None, ctypes.byref(p), None) == S.SEEDS_E_INVAL
+    assert L.seeds_server_submit(None, None, 8, 8, 24, 1, 1, None, 0, None) == S.SEEDS_E_INVAL
+    assert L.seeds_server_step(None, None) == S.SEEDS_E_INVAL
+    assert L.seeds_server_destroy(None) == S.SEEDS_OK
+
+
+def test_server_without_a_device_reports_device_error(S):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = S.seeds_server_default_params()
+    p.hbm_budget_bytes = 64 << 20
+    srv = ctypes.c_void_p()
+    assert S.lib().seeds_server_create(ctypes.byref(srv), ctypes.byref(p), None) in (
+        S.SEEDS_E_DEVICE, S.SEEDS_E_NOMEM)
+    assert not srv.value
