@@ -23,6 +23,14 @@ initial grid, pixel-level updates only (one level), SEEDS with 3 levels - and
 reports the metrics of Sec. 6.1 (UE, CUE, ASA, BR with eps 2) against the
 images' Voronoi region maps, computed on the device.
 
+`--workload serve` replays a request trace through the serving engine:
+Poisson arrivals at 2000 requests/s of 640x480 (70%), 1920x1080 (25%) and
+3840x2160 (5%) images, K = pixels/2000, 4 levels; 500 warm-up requests, then
+4000 timed ones. Latency runs from a request's arrival to its labels in host
+memory; value is the timed requests' pixels over the time from the first
+timed arrival to the last completion. The line also gives the plain path
+(single-image contexts back to back) on the same requests.
+
 `--workload batch64` measures the mixed batch instead: 64 synthetic images,
 W ~ U{320..1920}, H ~ U{240..1080}, 50-600 Voronoi regions, noise sigma in
 [4,16], K ~ U{200..2000} clamped to N/256, 3-4 levels, 5 bins, 4 sweeps,
@@ -481,10 +489,176 @@ def run_quality(args) -> int:
     return 0
 
 
+def run_serve(args) -> int:
+    import numpy as np
+    import torch
+
+    from paper_1309_3848_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build(force=True)
+    from paper_1309_3848_amd import seeds as S
+    from paper_1309_3848_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rate, n_warm, n_timed = args.rate, args.warm_requests, args.requests
+    classes = [(480, 640, 0.70, 24), (1080, 1920, 0.25, 8), (2160, 3840, 0.05, 2)]
+    # a pool of distinct images per size (results depend only on the image,
+    # so requests reuse them); region counts scale with the area
+    pool, pool_np = [], []
+    for ci, (H, W, _, cnt) in enumerate(classes):
+        imgs = [synth.voronoi_image(H, W, max(30, H * W // 5500), 8.0, 5000 + 100 * ci + j)
+                for j in range(cnt)]
+        pool_np.append(imgs)
+        pool.append([torch.from_numpy(im).to(dev) for im in imgs])
+    # the request trace: Poisson arrivals, size class by its share
+    rng = np.random.Generator(np.random.PCG64(5))
+    total = n_warm + n_timed
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=total))
+    cls_of = rng.choice(len(classes), size=total, p=[c[2] for c in classes])
+    pick = [int(rng.integers(0, classes[c][3])) for c in cls_of]
+    K_of = [classes[c][0] * classes[c][1] // 2000 for c in cls_of]
+    # pinned host outputs, reused once a request is reported
+    free_out = [[torch.empty((H, W), dtype=torch.int32, pin_memory=True) for _ in range(n)]
+                for (H, W, _, _), n in zip(classes, (192, 96, 24))]
+    stream = torch.cuda.current_stream()
+    params = S.seeds_server_default_params()
+    params.iters_per_level, params.max_levels = ITERS, LEVELS
+    params.hbm_budget_bytes, params.max_inflight = args.budget_gib << 30, 1024
+    srv = S.seeds_server_create(params, stream)
+    done_at = np.full(total, np.nan)
+    owner, out_of = {}, {}
+    kept = {}
+    nxt, completed = 0, 0
+    t0 = time.perf_counter()
+    while completed < total:
+        now = time.perf_counter() - t0
+        while nxt < total and arrivals[nxt] <= now:
+            c = cls_of[nxt]
+            if not free_out[c]:
+                break
+            out = free_out[c].pop()
+            rid = S.seeds_server_submit(srv, pool[c][pick[nxt]], K_of[nxt], LEVELS, out)
+            owner[rid], out_of[rid] = nxt, out
+            nxt += 1
+        pending = S.seeds_server_step(srv) if (owner or nxt < total) else 0
+        for rid in S.seeds_server_poll(srv):
+            i = owner.pop(rid)
+            done_at[i] = time.perf_counter() - t0
+            out = out_of.pop(rid)
+            if len(kept) < 12 and cls_of[i] == 0 and pick[i] not in kept:
+                kept[pick[i]] = out.clone()       # a few results for the checks below
+            free_out[cls_of[i]].append(out)
+            completed += 1
+        if pending == 0 and nxt < total and not owner:
+            wait = arrivals[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.001))
+    stats = S.seeds_server_get_stats(srv)
+    S.seeds_server_destroy(srv)
+    lat = (done_at - arrivals)[n_warm:] * 1e3
+    px = np.array([classes[c][0] * classes[c][1] for c in cls_of])
+    span = done_at[n_warm:].max() - arrivals[n_warm]
+    served_mpx = px[n_warm:].sum() / span / 1e6
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    # the plain path on the same requests: single-image contexts one after
+    # another; its latency under the same arrivals follows from a FIFO queue
+    ctxs = {}
+    outs_dev = [torch.empty((H, W), dtype=torch.int32, device=dev) for (H, W, _, _) in classes]
+    for c, (H, W, _, cnt) in enumerate(classes):
+        for j in range(cnt):
+            ctxs[c, j] = S.seeds_init(pool[c][j], H * W // 2000,
+                                      S.make_params(LEVELS, BINS, ITERS, GAMMA, RULE), stream)
+    def plain(i):
+        c, j = cls_of[i], pick[i]
+        S.seeds_reinit(ctxs[c, j], pool[c][j], stream)
+        S.seeds_refine(ctxs[c, j], stream)
+        S.seeds_labels(ctxs[c, j], outs_dev[c], stream)
+    for i in range(min(50, total)):
+        plain(i)
+    torch.cuda.synchronize()
+    service = {}
+    for c in range(len(classes)):
+        idx = [i for i in range(n_warm, total) if cls_of[i] == c][:40]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in idx:
+            plain(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        service[c] = e0.elapsed_time(e1) / max(1, len(idx)) / 1e3
+    plain_same = True
+    for j, lab in kept.items():
+        S.seeds_reinit(ctxs[0, j], pool[0][j], stream)
+        S.seeds_refine(ctxs[0, j], stream)
+        S.seeds_labels(ctxs[0, j], outs_dev[0], stream)
+        plain_same &= bool(torch.equal(outs_dev[0].cpu(), lab))
+    for cx in ctxs.values():
+        S.seeds_destroy(cx)
+    finish, plain_lat = 0.0, []
+    for i in range(total):
+        finish = max(finish, arrivals[i]) + service[cls_of[i]]
+        if i >= n_warm:
+            plain_lat.append((finish - arrivals[i]) * 1e3)
+    plain_span = finish - arrivals[n_warm]
+    result = {
+        "metric": METRIC, "value": round(served_mpx, 2), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": n_timed, "warmup": n_warm, "ms_per_step": round(span * 1e3 / n_timed, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {rate:g} req/s of RGB u8 images, "
+                               "70% 640x480, 25% 1920x1080, 5% 3840x2160 (Voronoi + gradient + "
+                               "noise sigma 8; a pool of 24/8/2 distinct images per size); "
+                               "K = pixels/2000, 4 levels, 5 bins, 4 sweeps, gamma 1, Prop. 1 "
+                               "rule; labels to pinned host memory; continuous batching server "
+                               f"with a {args.budget_gib} GiB budget",
+                   "rate_req_s": rate, "offered_mpx_s": round(float(px.mean()) * rate / 1e6, 1),
+                   "requests_timed": n_timed, "requests_warmup": n_warm,
+                   "step": "one request, arrival to labels in host memory"},
+        "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+        "server": {"ticks": stats["ticks"], "peak_inflight": stats["peak_inflight"],
+                   "peak_bytes_in_use": stats["peak_bytes_in_use"]},
+        "plain_path": {"value": round(px[n_warm:].sum() / plain_span / 1e6, 2),
+                       "unit": "Mpixel/s", "p50_ms": round(float(np.percentile(plain_lat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(plain_lat, 99)), 3),
+                       "service_ms": {f"{classes[c][1]}x{classes[c][0]}": round(v * 1e3, 3)
+                                      for c, v in service.items()},
+                       "note": "single-image contexts back to back; latency from a FIFO queue "
+                               "over the same arrivals and measured service times",
+                       "labels_equal_to_served": plain_same},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t2 = time.perf_counter()
+        same, used = True, 0
+        for j, lab in kept.items():
+            if used >= 2 and time.perf_counter() - t2 >= args.cpu_seconds:
+                break
+            ref, _, _ = oracle.seeds(pool_np[0][j], 480 * 640 // 2000, LEVELS, BINS, ITERS,
+                                     GAMMA, RULE)
+            same &= bool(np.array_equal(ref, lab.numpy()))
+            used += 1
+        cpu_s = time.perf_counter() - t2
+        result["cpu_baseline"] = {
+            "value": round(used * 480 * 640 / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{used} served 640x480 requests recomputed by the single-threaded C "
+                      f"oracle, {cpu_s:.1f} s"}
+        result["bitexact_vs_oracle"] = same
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single1080p", "batch64", "stream4k", "quality"],
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: timed requests")
+    ap.add_argument("--warm-requests", type=int, default=500, help="serve: warm-up requests")
+    ap.add_argument("--budget-gib", type=int, default=8, help="serve: server memory budget")
+    ap.add_argument("--workload", choices=["single1080p", "batch64", "stream4k", "quality", "serve"],
                     default="single1080p")
     ap.add_argument("--frames", type=int, default=300, help="stream4k: frames of the stream")
     ap.add_argument("--steps", type=int, default=None)
@@ -499,6 +673,10 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(images are independent: several GPUs would each refine their own images)", file=sys.stderr)
         return 2
+    if args.workload == "serve":
+        args.steps = args.requests if args.steps is None else args.steps
+        args.warmup = args.warm_requests if args.warmup is None else args.warmup
+        return run_serve(args)
     if args.workload == "quality":
         args.steps = 20 if args.steps is None else args.steps
         args.warmup = 3 if args.warmup is None else args.warmup

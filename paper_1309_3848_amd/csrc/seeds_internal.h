@@ -119,6 +119,34 @@ struct TickItem {
     int first, groups;   // logical workgroups [first, first + groups)
 };
 
+// The items of one mixed launch and a coarse index into them: coarse[c] is
+// the item holding logical workgroup c * kTickCoarse (nullptr: none, the
+// lookup searches all items).
+constexpr int kTickCoarse = 32;
+struct TickList {
+    const TickItem *items;
+    const int32_t *coarse;
+    int n;       // items
+    int ncoarse; // coarse entries
+};
+
+// Index of the item that holds logical workgroup lg: the last item whose
+// first workgroup is <= lg, searched between the coarse bounds.
+__host__ __device__ inline int find_tick_item(const TickList &l, int lg) {
+    int lo = 0, hi = l.n - 1;
+    if (l.coarse) {
+        const int c = lg / kTickCoarse;
+        lo = l.coarse[c];
+        if (c + 1 < l.ncoarse) hi = l.coarse[c + 1];
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (l.items[mid].first <= lg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Device view of a whole context for one launch.
 struct BatchArgs {
     const ImageDesc *imgs;  // device array, nimg entries
@@ -216,17 +244,13 @@ hipError_t launch_quality(const int32_t *lab, const int32_t *gt, int H, int W, i
 // Mixed launches of the serving engine: every item is one image. Phase items
 // run their own (level, class) with the Prop. 1 rule; `max_level` is the
 // largest level among them; replay as in launch_phase.
-hipError_t launch_phase_mixed(const BatchArgs &b, const TickItem *items, int nitems,
-                              int max_level, int par, int groups, int replay_groups,
-                              hipStream_t s);
-hipError_t launch_descend_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                                hipStream_t s);
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, int max_level, int par,
+                              int groups, int replay_groups, hipStream_t s);
+hipError_t launch_descend_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s);
 // Zero both state copies of every item's image, then initialise it (quantise,
 // grid, histograms) from item.rgb.
-hipError_t launch_zero_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                             hipStream_t s);
-hipError_t launch_init_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                             hipStream_t s);
+hipError_t launch_zero_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s);
+hipError_t launch_init_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s);
 // Workgroups of one image's state-zeroing share.
 constexpr int kZeroPerGroup = 4096;
 __host__ __device__ inline int zero_groups(const Dims &d) {

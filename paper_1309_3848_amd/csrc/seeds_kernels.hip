@@ -126,20 +126,9 @@ __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
 
 // Serving engine: items of newly admitted images. Their state regions are
 // zeroed by one launch (both copies), then initialised by the next.
-__device__ __forceinline__ int find_init_item(const TickItem *items, int n, int lg) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].first <= lg) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(kThreads) void k_zero_mixed(BatchArgs b, const TickItem *items,
-                                                         int nitems) {
+__global__ __launch_bounds__(kThreads) void k_zero_mixed(BatchArgs b, TickList l) {
     const int lg = xcd_group();
-    const TickItem &it = items[find_init_item(items, nitems, lg)];
+    const TickItem &it = l.items[find_tick_item(l, lg)];
     const int64_t n = (int64_t)it.g.d.K * it.g.d.hs + it.g.d.K;
     const int64_t lo = (int64_t)(lg - it.first) * kZeroPerGroup;
     const int64_t hi = min(n, lo + kZeroPerGroup);
@@ -150,11 +139,10 @@ __global__ __launch_bounds__(kThreads) void k_zero_mixed(BatchArgs b, const Tick
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_init_mixed(BatchArgs b, const TickItem *items,
-                                                         int nitems) {
+__global__ __launch_bounds__(kThreads) void k_init_mixed(BatchArgs b, TickList l) {
     __shared__ InitSlots sl;
     const int lg = xcd_group();
-    const TickItem &it = items[find_init_item(items, nitems, lg)];
+    const TickItem &it = l.items[find_tick_item(l, lg)];
     init_image(b, it.g, it.rgb, it.pitch, lg - it.first, sl);
 }
 
@@ -317,15 +305,13 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
     return hipGetLastError();
 }
 
-hipError_t launch_zero_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_mixed, dim3(groups), dim3(kThreads), 0, s, b, items, nitems);
+hipError_t launch_zero_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_mixed, dim3(groups), dim3(kThreads), 0, s, b, l);
     return hipGetLastError();
 }
 
-hipError_t launch_init_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_init_mixed, dim3(groups), dim3(kThreads), 0, s, b, items, nitems);
+hipError_t launch_init_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_mixed, dim3(groups), dim3(kThreads), 0, s, b, l);
     return hipGetLastError();
 }
 

@@ -90,37 +90,24 @@ __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const
         pass, stamp, replay_groups);
 }
 
-// Item of a mixed launch that holds logical workgroup lg: the last item whose
-// first workgroup is <= lg (items are sorted by `first`, none is empty).
-__device__ __forceinline__ int find_item(const TickItem *items, int n, int lg) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].first <= lg) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // A mixed launch: every item is one image at its own phase (level, class).
 // Only the Prop. 1 rule (one pass per phase) runs this way.
 template <bool BIG>
-__global__ __launch_bounds__(kPT) void k_phase_mixed(BatchArgs b, const TickItem *items,
-                                                     int nitems, int par, int replay_groups) {
+__global__ __launch_bounds__(kPT) void k_phase_mixed(BatchArgs b, TickList l, int par,
+                                                     int replay_groups) {
     phase_body<BIG>(
         b,
         [&]() {
             const int lg = xcd_group();
-            const TickItem &it = items[find_item(items, nitems, lg)];
+            const TickItem &it = l.items[find_tick_item(l, lg)];
             return PhaseWork{make_view(b, it.g, lg - it.first, it.groups), it.level, it.cls};
         },
         par, 0, 0u, replay_groups);
 }
 
-__global__ __launch_bounds__(kPT) void k_descend_mixed(BatchArgs b, const TickItem *items,
-                                                       int nitems) {
+__global__ __launch_bounds__(kPT) void k_descend_mixed(BatchArgs b, TickList l) {
     const int lg = xcd_group();
-    const TickItem &it = items[find_item(items, nitems, lg)];
+    const TickItem &it = l.items[find_tick_item(l, lg)];
     descend(make_view(b, it.g, lg - it.first, it.groups), it.level);
 }
 
@@ -170,18 +157,16 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
     return hipGetLastError();
 }
 
-hipError_t launch_phase_mixed(const BatchArgs &b, const TickItem *items, int nitems,
-                              int max_level, int par, int groups, int replay_groups,
-                              hipStream_t s) {
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, int max_level, int par,
+                              int groups, int replay_groups, hipStream_t s) {
     const int lds = max_level == 0 ? 0 : kPT * seg_ppl(max_level);
     auto fn = max_level >= 4 ? k_phase_mixed<true> : k_phase_mixed<false>;
-    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, items, nitems, par, replay_groups);
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups);
     return hipGetLastError();
 }
 
-hipError_t launch_descend_mixed(const BatchArgs &b, const TickItem *items, int nitems, int groups,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_descend_mixed, dim3(groups), dim3(kPT), 0, s, b, items, nitems);
+hipError_t launch_descend_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(k_descend_mixed, dim3(groups), dim3(kPT), 0, s, b, l);
     return hipGetLastError();
 }
 

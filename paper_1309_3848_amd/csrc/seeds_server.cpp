@@ -72,6 +72,7 @@ private:
 
 constexpr size_t kGran = 256;  // allocation granule (bytes / 4-byte elements x 64)
 constexpr int kRing = 8;       // ticks the host may run ahead of the device
+constexpr int kCoarseCap = 1 << 16;  // coarse index entries per tick (all lists)
 
 struct Request {
     int64_t id;
@@ -110,13 +111,15 @@ struct seeds_server {
     seeds_server_params p;
     int device = 0;
     hipStream_t s = nullptr;
+    hipStream_t copy = nullptr;    // label outputs, overlapped with the ticks
+    hipEvent_t gate[kRing] = {};   // end of a tick's kernels, for the copy stream
     void *slab = nullptr;
     uint8_t *px_base = nullptr;
     size_t px_size = 0, st_size = 0;
     Arenas ar{};
     int log_cap = 1, g_cap = 1, g_used = 0;
     FreeList px, st;
-    size_t ring_bytes = 0;
+    size_t ring_bytes = 0, items_bytes = 0;
     uint8_t *ring_host = nullptr;  // pinned, kRing slots
     uint8_t *ring_dev = nullptr;   // device, kRing slots
     uint32_t *flag_host = nullptr; // pinned copy of the device error flag
@@ -142,11 +145,15 @@ void destroy_request(Request *r) {
     delete r;
 }
 
-void release_request(seeds_server *sv, Request *r) {
+hipError_t release_request(seeds_server *sv, Request *r) {
+    // the labels copy reads the pixel region on the copy stream: later ticks
+    // on the main stream, which may reuse it, wait for that copy
+    hipError_t e = hipStreamWaitEvent(sv->s, r->done, 0);
     sv->px.release(r->px_off, r->px_len);
     sv->st.release(r->st_off, r->st_len);
     sv->g_used -= r->groups_max;
     sv->stats.bytes_in_use -= (int64_t)(r->px_len + r->st_len * 8);
+    return e;
 }
 
 bool try_admit(seeds_server *sv, Request *r) {
@@ -242,7 +249,8 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
     sv->g_cap = (int)std::min<size_t>(budget / 100 * 32 / (2 * (size_t)sv->log_cap * 8), 1 << 26);
     sv->px = FreeList(sv->px_size);
     sv->st = FreeList(sv->st_size);
-    sv->ring_bytes = round_up((size_t)4 * p->max_inflight * sizeof(TickItem), kGran);
+    sv->items_bytes = round_up((size_t)4 * p->max_inflight * sizeof(TickItem), kGran);
+    sv->ring_bytes = sv->items_bytes + kCoarseCap * sizeof(int32_t);
     size_t off = 0;
     auto take = [&](size_t n) { const size_t o = off; off += round_up(n, kGran); return o; };
     const size_t o_px = take(sv->px_size), o_st = take(2 * sv->st_size * 4);
@@ -253,8 +261,11 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->ring_host, kRing * sv->ring_bytes, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->flag_host, 64, 0);
     if (e == hipSuccess) *sv->flag_host = 0;
-    for (int i = 0; e == hipSuccess && i < kRing; ++i)
+    for (int i = 0; e == hipSuccess && i < kRing; ++i) {
         e = hipEventCreateWithFlags(&sv->ring_ev[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->gate[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         seeds_server_destroy(sv);
@@ -357,7 +368,8 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     for (auto it = sv->finishing.begin(); it != sv->finishing.end();) {
         Request *r = *it;
         if (r->finish_tick <= t - 2) {
-            release_request(sv, r);
+            hipError_t e = release_request(sv, r);
+            if (e != hipSuccess) return srv_device_error(sv, e, "stream wait");
             it = sv->finishing.erase(it);
             if (r->reported) destroy_request(r);
         } else {
@@ -433,21 +445,53 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
         phase_groups_total += gr;
         max_level = std::max(max_level, pr.second.first);
     }
+    // coarse indexes of the four lists, after the items in the same slot
+    int32_t *coarse_host = (int32_t *)(sv->ring_host + slot * sv->ring_bytes + sv->items_bytes);
+    int ncoarse_used = 0;
+    const uint8_t *slot_dev = sv->ring_dev + slot * sv->ring_bytes;
+    const TickItem *dev_items = (const TickItem *)slot_dev;
+    const int32_t *dev_coarse = (const int32_t *)(slot_dev + sv->items_bytes);
+    auto make_list = [&](int i0, int i1, int groups) {
+        TickList l;
+        l.items = dev_items + i0;
+        l.n = i1 - i0;
+        l.coarse = nullptr;
+        l.ncoarse = 0;
+        const int nc = (groups + kTickCoarse - 1) / kTickCoarse;
+        if (l.n > 1 && ncoarse_used + nc <= kCoarseCap) {
+            int it = i0;
+            for (int c = 0; c < nc; ++c) {
+                const int lg = c * kTickCoarse;
+                while (it + 1 < i1 && items[it + 1].first <= lg) ++it;
+                coarse_host[ncoarse_used + c] = it - i0;
+            }
+            l.coarse = dev_coarse + ncoarse_used;
+            l.ncoarse = nc;
+            ncoarse_used += nc;
+        }
+        return l;
+    };
+    const TickList zero_l = make_list(zero0, init0, zero_groups_total);
+    const TickList init_l = make_list(init0, desc0, init_groups_total);
+    const TickList desc_l = make_list(desc0, phase0, desc_groups_total);
+    const TickList phase_l = make_list(phase0, n, phase_groups_total);
     hipError_t e = hipSuccess;
-    const TickItem *dev_items = (const TickItem *)(sv->ring_dev + slot * sv->ring_bytes);
     if (n > 0)
         e = hipMemcpyAsync((void *)dev_items, items, n * sizeof(TickItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && ncoarse_used > 0)
+        e = hipMemcpyAsync((void *)dev_coarse, coarse_host, ncoarse_used * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s);
     const BatchArgs b = server_args(sv);
     if (e == hipSuccess && zero_groups_total > 0)
-        e = launch_zero_mixed(b, dev_items + zero0, init0 - zero0, zero_groups_total, s);
+        e = launch_zero_mixed(b, zero_l, zero_groups_total, s);
     if (e == hipSuccess && init_groups_total > 0)
-        e = launch_init_mixed(b, dev_items + init0, desc0 - init0, init_groups_total, s);
+        e = launch_init_mixed(b, init_l, init_groups_total, s);
     if (e == hipSuccess && desc_groups_total > 0)
-        e = launch_descend_mixed(b, dev_items + desc0, phase0 - desc0, desc_groups_total, s);
+        e = launch_descend_mixed(b, desc_l, desc_groups_total, s);
     if (e == hipSuccess) {
         if (phase_groups_total > 0) {
-            e = launch_phase_mixed(b, dev_items + phase0, n - phase0, max_level, sv->par,
-                                   phase_groups_total, sv->prev_groups, s);
+            e = launch_phase_mixed(b, phase_l, max_level, sv->par, phase_groups_total,
+                                   sv->prev_groups, s);
             sv->prev_groups = phase_groups_total;
             sv->par ^= 1;
         } else if (sv->prev_groups > 0) {
@@ -456,13 +500,19 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
             sv->prev_groups = 0;
         }
     }
-    // labels of the images whose schedule ended in this tick
+    // labels of the images whose schedule ended in this tick, copied on the
+    // copy stream once this tick's kernels are done
+    if (e == hipSuccess && !finished_now.empty()) {
+        e = hipEventRecord(sv->gate[slot], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sv->copy, sv->gate[slot], 0);
+    }
     for (Request *r : finished_now) {
         if (e != hipSuccess) break;
         const size_t bytes = (size_t)r->d.H * r->d.W * 4;
         e = hipMemcpyAsync(r->out, sv->ar.lab + r->g.lab, bytes,
-                           r->out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipEventRecord(r->done, s);
+                           r->out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           sv->copy);
+        if (e == hipSuccess) e = hipEventRecord(r->done, sv->copy);
         r->finish_tick = t;
         sv->finishing.push_back(r);
         sv->unreported.push_back(r);
@@ -470,7 +520,7 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     }
     // with the labels, the kernels' error flag (a full move log) comes back
     if (e == hipSuccess && !finished_now.empty())
-        e = hipMemcpyAsync(sv->flag_host, sv->ar.sync + 2, 4, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(sv->flag_host, sv->ar.sync + 2, 4, hipMemcpyDeviceToHost, sv->copy);
     if (e == hipSuccess) e = hipEventRecord(sv->ring_ev[slot], s);
     if (e != hipSuccess) return srv_device_error(sv, e, "tick launch");
     sv->ring_used[slot] = true;
@@ -524,6 +574,10 @@ seeds_status seeds_server_get_stats(const seeds_server *sv, seeds_server_stats *
 seeds_status seeds_server_destroy(seeds_server *sv) {
     if (!sv) return SEEDS_OK;
     hipError_t e = hipStreamSynchronize(sv->s);
+    if (sv->copy) {
+        hipError_t e2 = hipStreamSynchronize(sv->copy);
+        if (e == hipSuccess) e = e2;
+    }
     std::vector<Request *> all(sv->queue.begin(), sv->queue.end());
     all.insert(all.end(), sv->running.begin(), sv->running.end());
     all.insert(all.end(), sv->finishing.begin(), sv->finishing.end());
@@ -532,6 +586,9 @@ seeds_status seeds_server_destroy(seeds_server *sv) {
     for (Request *r : all) destroy_request(r);
     for (auto &ev : sv->ring_ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto &ev : sv->gate)
+        if (ev) (void)hipEventDestroy(ev);
+    if (sv->copy) (void)hipStreamDestroy(sv->copy);
     if (sv->ring_host) (void)hipHostFree(sv->ring_host);
     if (sv->flag_host) (void)hipHostFree(sv->flag_host);
     if (sv->slab) (void)hipFree(sv->slab);
