@@ -128,6 +128,7 @@ struct TickList {
     const int32_t *coarse;
     int n;       // items
     int ncoarse; // coarse entries
+    int hs;      // histogram row stride (shared by every image of a server)
 };
 
 // Index of the item that holds logical workgroup lg: the last item whose
@@ -162,6 +163,21 @@ constexpr int kPersistentThreads = 256;
 // pixels per lane, SEG * PPL = s * s.
 __host__ __device__ inline int seg_lanes(int level) { return level >= 3 ? 64 : 1 << (2 * level); }
 __host__ __device__ inline int seg_ppl(int level) { return level >= 3 ? 1 << (2 * level - 6) : 1; }
+
+// Dynamic LDS of a block phase at `level` (hs: histogram row stride): blocks
+// of more than 64 pixels stage their bins (one byte per pixel), blocks of 16
+// to 64 pixels count their bins in one LDS histogram row per segment.
+__host__ __device__ inline int phase_lds_bytes(int level, int hs) {
+    if (level == 0) return 0;
+    if (seg_ppl(level) > 1) return kPersistentThreads * seg_ppl(level);
+    return seg_lanes(level) >= 16 ? (kPersistentThreads / seg_lanes(level)) * hs * 4 : 0;
+}
+// The most any level up to max_level needs.
+__host__ __device__ inline int phase_lds_bytes_upto(int max_level, int hs) {
+    int b = 0;
+    for (int l = 1; l <= max_level; ++l) b = b > phase_lds_bytes(l, hs) ? b : phase_lds_bytes(l, hs);
+    return b;
+}
 
 // Units one workgroup of a phase launch handles at `level`, and workgroups an
 // image needs for one phase of class cls.

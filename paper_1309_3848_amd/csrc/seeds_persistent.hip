@@ -128,9 +128,7 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
 
 PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu) {
     PersistentGeom g;
-    int ppl_max = 1;
-    for (int l = 1; l < d.L; ++l) ppl_max = max(ppl_max, seg_ppl(l));
-    g.lds_bytes = kPT * ppl_max;
+    g.lds_bytes = max(1, phase_lds_bytes_upto(d.L - 1, d.hs));
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         cus < 1)

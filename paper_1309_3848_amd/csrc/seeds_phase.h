@@ -213,6 +213,24 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
 }
 
 // ---------------------------------------------------------------------------
+// Sparse block histogram in LDS for blocks of 16 to 64 pixels (one pixel per
+// lane; a segment of SEG lanes, all in one wavefront, owns one zeroed row h of
+// the histogram stride): every lane adds its pixel to h[j]; the lane that
+// found h[j] at 0 leads its bin, reads the bin's count h_l(j) and clears the
+// entry again. Any one lead lane per bin gives the same integer sums. A
+// wavefront's LDS operations complete in issue order, so the leader's read
+// follows every lane's addition.
+__device__ __forceinline__ void lds_bins(int j, int32_t *h, int &cnt, bool &first) {
+    cnt = 0;
+    first = false;
+    if (j == 0xFF) return;
+    first = atomicAdd(&h[j], 1) == 0;
+    if (first) {
+        cnt = __hip_atomic_load(&h[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_store(&h[j], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+}
+
 // Sparse block histogram with wavefront ballots, for blocks of at most 64
 // pixels (one pixel per lane, segments of SEG lanes inside one wavefront):
 // for the lane's bin j (0xFF = no pixel), cnt = h_l(j) of its segment's block
@@ -281,6 +299,12 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
     const bool exact = d.rule == SEEDS_BLOCK_EXACT;
     uint8_t *mine = sbin + seg * NPX;
     (void)mine;
+    // segments of 16 or more one-pixel lanes count their block's bins in LDS
+    constexpr bool kLdsBins = PPL == 1 && SEG >= 16;
+    int32_t *seg_hist = reinterpret_cast<int32_t *>(sbin) + seg * d.hs;
+    if constexpr (kLdsBins) {
+        for (int i = lane; i < d.hs; i += SEG) seg_hist[i] = 0;
+    }
     const int grp = v.grp;
     for (int r = 0; r < rounds; ++r) {
         const int unit = (r * v.ngroups + grp) * SEGS + seg;
@@ -311,7 +335,10 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         if constexpr (PPL == 1) {
             const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
             j1 = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
-            ballot_bins<SEG>(j1, cnt1, first1);
+            if constexpr (kLdsBins)
+                lds_bins(j1, seg_hist, cnt1, first1);
+            else
+                ballot_bins<SEG>(j1, cnt1, first1);
         } else {
 #pragma unroll 4
             for (int tt = 0; tt < PPL; ++tt) {

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kPT) void k_descend(BatchArgs b, ImageDesc one, con
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
                         int replay_groups, hipStream_t s) {
-    const int lds = level == 0 ? 0 : kPT * seg_ppl(level);
+    const int lds = phase_lds_bytes(level, one.d.hs);
     const bool batch = b.nimg > 1;
     auto fn = max_level >= 4 ? (batch ? k_phase<true, true> : k_phase<true, false>)
                              : (batch ? k_phase<false, true> : k_phase<false, false>);
@@ -159,7 +159,7 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
 
 hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, int max_level, int par,
                               int groups, int replay_groups, hipStream_t s) {
-    const int lds = max_level == 0 ? 0 : kPT * seg_ppl(max_level);
+    const int lds = phase_lds_bytes_upto(max_level, l.hs);
     auto fn = max_level >= 4 ? k_phase_mixed<true> : k_phase_mixed<false>;
     hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups);
     return hipGetLastError();

@@ -457,6 +457,7 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
         l.n = i1 - i0;
         l.coarse = nullptr;
         l.ncoarse = 0;
+        l.hs = hist_stride(sv->p.bins_per_channel * sv->p.bins_per_channel * sv->p.bins_per_channel);
         const int nc = (groups + kTickCoarse - 1) / kTickCoarse;
         if (l.n > 1 && ncoarse_used + nc <= kCoarseCap) {
             int it = i0;
