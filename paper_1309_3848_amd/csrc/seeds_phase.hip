@@ -33,7 +33,9 @@ struct PhaseWork {
 
 // The body shared by every phase launch. `find` yields the workgroup's work;
 // it runs after the replay prefetch is issued so that the two overlap.
-template <bool BIG, typename Find>
+// KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
+// workgroup from its work).
+template <bool BIG, int KINDS, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups) {
     extern __shared__ uint8_t sbin[];
@@ -58,10 +60,16 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     }
     const PhaseWork w = find();
     int2 *mylog = b.ar.log + ((int64_t)par * b.log_groups + blockIdx.x) * b.log_cap;
-    if (w.level == 0)
+    if constexpr (KINDS == 1) {
         pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
-    else
+    } else if constexpr (KINDS == 2) {
         block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
+    } else {
+        if (w.level == 0)
+            pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
+        else
+            block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
+    }
     if (replay_own) {
         const int n = min(pre_n, b.log_cap);
         if ((int)threadIdx.x < min(n, kPre)) atomicAdd(&W[pre.x], pre.y);
@@ -81,11 +89,14 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     if (threadIdx.x == 0) b.ar.log_n[(int64_t)par * b.log_groups + blockIdx.x] = min(t.n, b.log_cap);
 }
 
-template <bool BIG, bool BATCH>
-__global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const int2 *map,
-                                               int level, int cls, int par, int pass,
-                                               uint32_t stamp, int replay_groups) {
-    phase_body<BIG>(
+// PIXEL selects the pixel-level or the block-level code: each variant holds
+// only its own registers, and the block variant of the common hierarchies
+// (BIG = false) fits six wavefronts per SIMD without spilling.
+template <bool BIG, bool BATCH, bool PIXEL>
+__global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
+    BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
+    uint32_t stamp, int replay_groups) {
+    phase_body<BIG, PIXEL ? 1 : 2>(
         b, [&]() { return PhaseWork{resolve<BATCH>(b, one, map, level, cls), level, cls}; }, par,
         pass, stamp, replay_groups);
 }
@@ -95,7 +106,7 @@ __global__ __launch_bounds__(kPT) void k_phase(BatchArgs b, ImageDesc one, const
 template <bool BIG>
 __global__ __launch_bounds__(kPT) void k_phase_mixed(BatchArgs b, TickList l, int par,
                                                      int replay_groups) {
-    phase_body<BIG>(
+    phase_body<BIG, 3>(
         b,
         [&]() {
             const int lg = xcd_group();
@@ -150,8 +161,10 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
                         int replay_groups, hipStream_t s) {
     const int lds = phase_lds_bytes(level, one.d.hs);
     const bool batch = b.nimg > 1;
-    auto fn = max_level >= 4 ? (batch ? k_phase<true, true> : k_phase<true, false>)
-                             : (batch ? k_phase<false, true> : k_phase<false, false>);
+    auto fn = level == 0 ? (batch ? k_phase<false, true, true> : k_phase<false, false, true>)
+              : max_level >= 4
+                  ? (batch ? k_phase<true, true, false> : k_phase<true, false, false>)
+                  : (batch ? k_phase<false, true, false> : k_phase<false, false, false>);
     hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, one, map, level, cls, par, pass,
                        stamp, replay_groups);
     return hipGetLastError();
