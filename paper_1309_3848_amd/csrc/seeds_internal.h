@@ -258,10 +258,12 @@ hipError_t launch_quality(const int32_t *lab, const int32_t *gt, int H, int W, i
                           int eps, int32_t *table, unsigned long long *cnt, hipStream_t s);
 
 // Mixed launches of the serving engine: every item is one image. Phase items
-// run their own (level, class) with the Prop. 1 rule; `max_level` is the
-// largest level among them; replay as in launch_phase.
-hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, int max_level, int par,
-                              int groups, int replay_groups, hipStream_t s);
+// run their own (level, class) with the Prop. 1 rule, all of them at pixel
+// level (pixel = true) or all at block levels up to max_level; replay as in
+// launch_phase; the launch's log slots start at slot_base.
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, bool pixel, int max_level,
+                              int par, int groups, int replay_groups, int slot_base,
+                              hipStream_t s);
 hipError_t launch_descend_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s);
 // Zero both state copies of every item's image, then initialise it (quantise,
 // grid, histograms) from item.rgb.

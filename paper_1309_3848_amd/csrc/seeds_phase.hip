@@ -37,7 +37,8 @@ struct PhaseWork {
 // workgroup from its work).
 template <bool BIG, int KINDS, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
-                                           uint32_t stamp, int replay_groups) {
+                                           uint32_t stamp, int replay_groups,
+                                           int slot_base = 0) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
     __shared__ PixelList pl;
@@ -59,7 +60,10 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
         if (threadIdx.x < kPre) pre = b.ar.log[own_slot * b.log_cap + threadIdx.x];
     }
     const PhaseWork w = find();
-    int2 *mylog = b.ar.log + ((int64_t)par * b.log_groups + blockIdx.x) * b.log_cap;
+    // this workgroup's log slot: a phase split over two launches gives the
+    // second one the slots after the first one's
+    const int64_t my_slot = (int64_t)par * b.log_groups + slot_base + blockIdx.x;
+    int2 *mylog = b.ar.log + my_slot * b.log_cap;
     if constexpr (KINDS == 1) {
         pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
     } else if constexpr (KINDS == 2) {
@@ -86,7 +90,7 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     if (pass == 1) return;
     table_flush(b, t, W, mylog);
     __syncthreads();
-    if (threadIdx.x == 0) b.ar.log_n[(int64_t)par * b.log_groups + blockIdx.x] = min(t.n, b.log_cap);
+    if (threadIdx.x == 0) b.ar.log_n[my_slot] = min(t.n, b.log_cap);
 }
 
 // PIXEL selects the pixel-level or the block-level code: each variant holds
@@ -102,18 +106,20 @@ __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
 }
 
 // A mixed launch: every item is one image at its own phase (level, class).
-// Only the Prop. 1 rule (one pass per phase) runs this way.
-template <bool BIG>
-__global__ __launch_bounds__(kPT) void k_phase_mixed(BatchArgs b, TickList l, int par,
-                                                     int replay_groups) {
-    phase_body<BIG, 3>(
+// Only the Prop. 1 rule (one pass per phase) runs this way. A tick runs its
+// pixel-level items and its block-level items as two launches of the two
+// kernel variants; the second takes the log slots after the first's.
+template <bool BIG, bool PIXEL>
+__global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase_mixed(
+    BatchArgs b, TickList l, int par, int replay_groups, int slot_base) {
+    phase_body<BIG, PIXEL ? 1 : 2>(
         b,
         [&]() {
             const int lg = xcd_group();
             const TickItem &it = l.items[find_tick_item(l, lg)];
             return PhaseWork{make_view(b, it.g, lg - it.first, it.groups), it.level, it.cls};
         },
-        par, 0, 0u, replay_groups);
+        par, 0, 0u, replay_groups, slot_base);
 }
 
 __global__ __launch_bounds__(kPT) void k_descend_mixed(BatchArgs b, TickList l) {
@@ -170,11 +176,13 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
     return hipGetLastError();
 }
 
-hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, int max_level, int par,
-                              int groups, int replay_groups, hipStream_t s) {
-    const int lds = phase_lds_bytes_upto(max_level, l.hs);
-    auto fn = max_level >= 4 ? k_phase_mixed<true> : k_phase_mixed<false>;
-    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups);
+hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, bool pixel, int max_level,
+                              int par, int groups, int replay_groups, int slot_base,
+                              hipStream_t s) {
+    const int lds = pixel ? 0 : phase_lds_bytes_upto(max_level, l.hs);
+    auto fn = pixel ? k_phase_mixed<false, true>
+                    : (max_level >= 4 ? k_phase_mixed<true, false> : k_phase_mixed<false, false>);
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups, slot_base);
     return hipGetLastError();
 }
 

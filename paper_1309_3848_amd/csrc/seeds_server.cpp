@@ -436,15 +436,26 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
         int c2;
         if (op != OP_PHASE || sched_next(r->d, peek, -1, &c2) == OP_END) finished_now.push_back(r);
     }
+    // phase items: pixel-level ones, then block-level ones (two launches)
     const int phase0 = n;
-    int phase_groups_total = 0, max_level = 0;
+    int pixel_groups = 0, block_groups = 0, max_level = 0;
     for (auto &pr : phase_of) {
+        if (pr.second.first != 0) continue;
+        const int gr = phase_groups(pr.first->d, 0, pr.second.second);
+        if (gr == 0) continue;
+        add(pr.first, 0, pr.second.second, pixel_groups, gr);
+        pixel_groups += gr;
+    }
+    const int block0 = n;
+    for (auto &pr : phase_of) {
+        if (pr.second.first == 0) continue;
         const int gr = phase_groups(pr.first->d, pr.second.first, pr.second.second);
         if (gr == 0) continue;
-        add(pr.first, pr.second.first, pr.second.second, phase_groups_total, gr);
-        phase_groups_total += gr;
+        add(pr.first, pr.second.first, pr.second.second, block_groups, gr);
+        block_groups += gr;
         max_level = std::max(max_level, pr.second.first);
     }
+    const int phase_groups_total = pixel_groups + block_groups;
     // coarse indexes of the four lists, after the items in the same slot
     int32_t *coarse_host = (int32_t *)(sv->ring_host + slot * sv->ring_bytes + sv->items_bytes);
     int ncoarse_used = 0;
@@ -475,7 +486,8 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     const TickList zero_l = make_list(zero0, init0, zero_groups_total);
     const TickList init_l = make_list(init0, desc0, init_groups_total);
     const TickList desc_l = make_list(desc0, phase0, desc_groups_total);
-    const TickList phase_l = make_list(phase0, n, phase_groups_total);
+    const TickList pixel_l = make_list(phase0, block0, pixel_groups);
+    const TickList block_l = make_list(block0, n, block_groups);
     hipError_t e = hipSuccess;
     if (n > 0)
         e = hipMemcpyAsync((void *)dev_items, items, n * sizeof(TickItem), hipMemcpyHostToDevice, s);
@@ -491,8 +503,15 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
         e = launch_descend_mixed(b, desc_l, desc_groups_total, s);
     if (e == hipSuccess) {
         if (phase_groups_total > 0) {
-            e = launch_phase_mixed(b, phase_l, max_level, sv->par, phase_groups_total,
-                                   sv->prev_groups, s);
+            // the first launch of the tick adds the previous tick's deltas
+            int replay = sv->prev_groups;
+            if (pixel_groups > 0) {
+                e = launch_phase_mixed(b, pixel_l, true, 0, sv->par, pixel_groups, replay, 0, s);
+                replay = 0;
+            }
+            if (e == hipSuccess && block_groups > 0)
+                e = launch_phase_mixed(b, block_l, false, max_level, sv->par, block_groups, replay,
+                                       pixel_groups, s);
             sv->prev_groups = phase_groups_total;
             sv->par ^= 1;
         } else if (sv->prev_groups > 0) {
