@@ -778,7 +778,7 @@ def main() -> int:
         "hbm_frac_step": round((refine_bytes + init_bytes + out_bytes) / (ms_per_step * 1e-3)
                                / 1e9 / HBM_PEAK_GBS, 6),
         "algorithmic_bytes_per_step": int(refine_bytes + init_bytes + out_bytes),
-        "roofline": {"bound": "hbm", "kernel": "k_phase (one phase of the schedule per launch)",
+        "roofline": {"bound": "hbm", "kernel": "k_phase (one phase of the schedule per launch; block-level and pixel-level variants)",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                      "algorithmic_bytes_per_launch": int(per_launch),
