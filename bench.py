@@ -11,6 +11,8 @@ Prop. 1 block rule.
 Prints one JSON line (rank 0). `roofline` reports the refine kernel against
 the HBM roofline with the algorithmic bytes of the schedule; `cpu_baseline`
 times the CPU oracle on the same image and checks the GPU labels against it.
+Before the warm-up the context's launch mapping is autotuned (seeds_autotune;
+the mapping never changes a result), unless --no-autotune.
 
 `--workload stream4k` measures a 300-frame 3840 x 2160 video stream: frame 0
 runs the whole hierarchy, every later frame is warm-started from the previous
@@ -138,6 +140,10 @@ def run_batch(args) -> int:
     stream = torch.cuda.current_stream()
     params = S.make_params(max(Ls), BINS, ITERS, GAMMA, RULE)
     ctx = S.seeds_batch_init(rgbs, Ks, params, levels=Ls, stream=stream)
+    tuning = None
+    if not args.no_autotune:
+        chosen, ms = S.seeds_autotune(ctx, 3, stream)
+        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 3) for m in ms]}
 
     def step():
         S.seeds_batch_reinit(ctx, rgbs, stream)
@@ -217,7 +223,7 @@ def run_batch(args) -> int:
                    "images": len(specs), "megapixels": round(npx / 1e6, 3),
                    "step": "batch reinit + refine + labels of every image (device)"},
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
-        "images_per_s": round(len(specs) * args.steps / wall, 1),
+        "images_per_s": round(len(specs) * args.steps / wall, 1), "tuning": tuning,
         "plain_path": {"ms_per_batch": round(solo_ms, 4),
                        "value": round(npx / (solo_ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
                        "labels_equal_to_batch": solo_same},
@@ -294,6 +300,10 @@ def run_stream(args) -> int:
 
     ctx = S.seeds_init(frames[0], SK, params, stream)
     keff = S.seeds_num_superpixels(ctx)
+    tuning = None
+    if not args.no_autotune:
+        chosen, ms = S.seeds_autotune(ctx, 3, stream)
+        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 3) for m in ms]}
     # warm-up on the first frames, then the timed pass over the whole stream
     for f in range(min(args.warmup, nfr)):
         (cold if f == 0 else warm)(ctx, f)
@@ -356,7 +366,7 @@ def run_stream(args) -> int:
                    "H": SH, "W": SW, "K": SK, "K_eff": keff, "frames": nfr,
                    "step": "one frame: warm start + refine + labels (device)"},
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
-        "frame0_ms": round(lat[0], 4), "frames_per_s": round(nfr / wall, 1),
+        "frame0_ms": round(lat[0], 4), "frames_per_s": round(nfr / wall, 1), "tuning": tuning,
         "cold_per_frame_p50_ms": round(cold_p50, 4),
         "frame_generation_s": round(gen_s, 1),
         "roofline": {"bound": "hbm", "kernel": "k_phase (pixel-level phase of one 4K frame)",
@@ -664,6 +674,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch mapping instead of timing the four settings "
+                         "(seeds_autotune) before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 64 MiB device-to-device copy (a known amount of HBM "
@@ -710,6 +723,10 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     ctx = S.seeds_init(rgb, K, params, stream)
     keff = S.seeds_num_superpixels(ctx)
+    tuning = None
+    if not args.no_autotune:
+        chosen, ms = S.seeds_autotune(ctx, 5, stream)
+        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 4) for m in ms]}
 
     def step():
         S.seeds_reinit(ctx, rgb, stream)
@@ -774,7 +791,7 @@ def main() -> int:
                    "H": H, "W": W, "K": K, "K_eff": keff, "levels": LEVELS, "bins": BINS,
                    "iters": ITERS, "gamma": GAMMA, "block_rule": "intersect",
                    "step": "reinit + refine + labels (device)"},
-        "p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
+        "p50_ms": round(p50, 4), "p99_ms": round(p99, 4), "tuning": tuning,
         "hbm_frac_step": round((refine_bytes + init_bytes + out_bytes) / (ms_per_step * 1e-3)
                                / 1e9 / HBM_PEAK_GBS, 6),
         "algorithmic_bytes_per_step": int(refine_bytes + init_bytes + out_bytes),

@@ -153,6 +153,36 @@ typedef enum {
  * is for single-image contexts (SEEDS_E_INVAL on a batch).                   */
 seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
 
+/* ---- Tuning ---------------------------------------------------------------
+ * How the per-phase launches map work to workgroups. The choice never changes
+ * a result: labels, histograms and sizes are the same for every setting.
+ *   pixel_compaction  1: pixel phases first test every pixel of the class
+ *                     cheaply and pack the movable ones into dense wavefronts
+ *                     for the full decision; 0: every thread decides its own
+ *                     pixel (more arithmetic, one dependent round of loads
+ *                     less).
+ *   xcd_remap         1: workgroups are numbered so that each of the eight
+ *                     XCDs works a contiguous band of the image (fewer L2
+ *                     misses); 0: hardware order.
+ * Default: both 1.                                                           */
+typedef struct {
+    int32_t pixel_compaction;
+    int32_t xcd_remap;
+} seeds_tuning;
+
+seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out);
+seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t);
+
+/* Time a whole refinement (reps runs after one warm-up, median) for each of
+ * the four settings on this context's own images and keep the fastest. The
+ * context is re-initialised from its images before every run and once more
+ * at the end, so it returns freshly initialised (as after seeds_reinit); the
+ * call waits for the stream. *chosen and ms_per_variant[4] (either may be
+ * NULL) receive the choice and the medians, variant v = 2 (1 - xcd_remap) +
+ * (1 - pixel_compaction). Not for SEEDS_LAUNCH_PERSISTENT; reps in [1,50].  */
+seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
+                            float *ms_per_variant, void *hip_stream);
+
 /* Wait for the stream and report device-side failures of earlier refine
  * calls (a grid barrier that timed out, an overflowing move log) as
  * SEEDS_E_DEVICE. seeds_labels and seeds_histograms with host outputs do the

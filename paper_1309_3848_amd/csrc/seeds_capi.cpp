@@ -89,6 +89,7 @@ struct seeds_ctx {
     int log_groups = 1, log_cap = 1;  // move-log shape of the per-phase launches
     PersistentGeom geom{};            // single image only
     int mode = SEEDS_LAUNCH_GRAPH;    // seeds_launch_mode
+    PhaseTuning tune;                 // mapping of the per-phase launches
     hipStream_t capture = nullptr;    // private stream used only to capture graphs
     CachedGraph graphs[kGraphSlots];
     int next_slot = 0;
@@ -250,13 +251,13 @@ seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_ou
             } else {
                 if (level > 0 && exact) {
                     e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 1, stamp, m.groups,
-                                     prev_groups, s);
+                                     prev_groups, ctx->tune, s);
                     if (e == hipSuccess)
                         e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 2, stamp,
-                                         m.groups, 0, s);
+                                         m.groups, 0, ctx->tune, s);
                 } else {
                     e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 0, stamp, m.groups,
-                                     prev_groups, s);
+                                     prev_groups, ctx->tune, s);
                 }
                 prev_groups = m.groups;
                 par ^= 1;
@@ -370,6 +371,15 @@ seeds_status check_device_flag(seeds_ctx *ctx, hipStream_t s) {
                                               : "persistent kernel: grid barrier timed out");
     }
     return SEEDS_OK;
+}
+
+// Drop every captured refinement (after a change of the launch mapping).
+void clear_graphs(seeds_ctx *ctx) {
+    for (auto &g : ctx->graphs)
+        if (g.valid) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.valid = false;
+        }
 }
 
 void destroy_ctx(seeds_ctx *ctx) {
@@ -898,6 +908,78 @@ seeds_status seeds_quality_metrics(const int32_t *labels, const int32_t *truth, 
     out->br_hits = (int64_t)cnt[3];
     out->br_total = (int64_t)cnt[4];
     return SEEDS_OK;
+}
+
+seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out) {
+    if (!ctx || !out) return fail(SEEDS_E_INVAL, "NULL argument");
+    out->pixel_compaction = ctx->tune.pixel_compact ? 1 : 0;
+    out->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
+    return SEEDS_OK;
+}
+
+seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t) {
+    if (!ctx || !t) return fail(SEEDS_E_INVAL, "NULL argument");
+    if ((t->pixel_compaction != 0 && t->pixel_compaction != 1) ||
+        (t->xcd_remap != 0 && t->xcd_remap != 1))
+        return fail(SEEDS_E_INVAL, "tuning fields are 0 or 1");
+    ctx->tune.pixel_compact = t->pixel_compaction != 0;
+    ctx->tune.xcd_remap = t->xcd_remap != 0;
+    clear_graphs(ctx);
+    return SEEDS_OK;
+}
+
+seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
+                            float *ms_per_variant, void *hip_stream) {
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    if (ctx->mode == SEEDS_LAUNCH_PERSISTENT)
+        return fail(SEEDS_E_INVAL, "autotuning applies to the per-phase launch modes");
+    if (reps < 1 || reps > 50) return fail(SEEDS_E_INVAL, "reps %d outside [1,50]", reps);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best_ms = 0;
+    int best = 0;
+    for (int v = 0; v < 4 && e == hipSuccess; ++v) {
+        ctx->tune.pixel_compact = (v & 1) == 0;
+        ctx->tune.xcd_remap = (v & 2) == 0;
+        clear_graphs(ctx);
+        std::vector<float> t;
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r = 0 warms up (capture)
+            st = start_schedule(ctx, s);
+            if (st != SEEDS_OK) break;
+            e = hipEventRecord(e0, s);
+            if (e != hipSuccess) break;
+            st = run_schedule(ctx, -1, nullptr, s);
+            if (st != SEEDS_OK) break;
+            e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t.push_back(ms);
+        }
+        if (st != SEEDS_OK || e != hipSuccess) break;
+        std::sort(t.begin(), t.end());
+        const float med = t[t.size() / 2];
+        if (ms_per_variant) ms_per_variant[v] = med;
+        if (v == 0 || med < best_ms) {
+            best_ms = med;
+            best = v;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != SEEDS_OK) return st;
+    if (e != hipSuccess) return device_error(ctx, e, "autotune timing");
+    ctx->tune.pixel_compact = (best & 1) == 0;
+    ctx->tune.xcd_remap = (best & 2) == 0;
+    clear_graphs(ctx);
+    if (chosen) {
+        chosen->pixel_compaction = ctx->tune.pixel_compact ? 1 : 0;
+        chosen->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
+    }
+    return start_schedule(ctx, s);
 }
 
 const char *seeds_last_error(void) { return g_err; }

@@ -230,9 +230,14 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
 // only, 2 exact-rule apply. replay_groups: workgroups of the previous phase
 // launch, whose logs (parity par ^ 1) this launch adds to its write copy.
 // max_level: the largest level of any image (selects the kernel variant).
+// Mapping choices of the per-phase launches (results never depend on them).
+struct PhaseTuning {
+    bool pixel_compact = true;  // pixel phases: pre-test and compaction
+    bool xcd_remap = true;      // workgroups numbered in contiguous bands per XCD
+};
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
-                        int replay_groups, hipStream_t s);
+                        int replay_groups, const PhaseTuning &tune, hipStream_t s);
 // Add the logs of the last phase launch (parity par, `groups` slots) to the
 // copy that phase read.
 hipError_t launch_final_replay(const BatchArgs &b, int par, int groups, hipStream_t s);

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
             if (phases > 0) replay(prev_log, min(prev_n, b.log_cap), W);
             ++stamp;
             if (sc.level == 0) {
-                pixel_phase(b, v, cls, par, t, cur_log, pl);
+                pixel_phase<true>(b, v, cls, par, t, cur_log, pl);
             } else if (d.rule == SEEDS_BLOCK_EXACT) {
                 block_phase_any<BIG>(b, v, sc.level, cls, par, 1, stamp, sbin, t, cur_log);
                 if (!grid_sync(sync, gen)) return;

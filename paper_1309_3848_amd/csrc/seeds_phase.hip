@@ -14,8 +14,8 @@ namespace {
 // group] = (image, rank among the image's workgroups).
 template <bool BATCH>
 __device__ __forceinline__ ImageView resolve(const BatchArgs &b, const ImageDesc &one,
-                                             const int2 *map, int level, int cls) {
-    const int lg = xcd_group();
+                                             const int2 *map, int level, int cls, int remap) {
+    const int lg = remap ? xcd_group() : (int)blockIdx.x;
     if constexpr (!BATCH) {
         return single_view(b, one, lg, gridDim.x);
     } else {
@@ -35,7 +35,7 @@ struct PhaseWork {
 // it runs after the replay prefetch is issued so that the two overlap.
 // KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
 // workgroup from its work).
-template <bool BIG, int KINDS, typename Find>
+template <bool BIG, int KINDS, bool COMPACT, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups,
                                            int slot_base = 0) {
@@ -65,12 +65,12 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     const int64_t my_slot = (int64_t)par * b.log_groups + slot_base + blockIdx.x;
     int2 *mylog = b.ar.log + my_slot * b.log_cap;
     if constexpr (KINDS == 1) {
-        pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
+        pixel_phase<COMPACT>(b, w.v, w.cls, par, t, mylog, pl);
     } else if constexpr (KINDS == 2) {
         block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     } else {
         if (w.level == 0)
-            pixel_phase(b, w.v, w.cls, par, t, mylog, pl);
+            pixel_phase<COMPACT>(b, w.v, w.cls, par, t, mylog, pl);
         else
             block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     }
@@ -96,13 +96,18 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
 // PIXEL selects the pixel-level or the block-level code: each variant holds
 // only its own registers, and the block variant of the common hierarchies
 // (BIG = false) fits six wavefronts per SIMD without spilling.
-template <bool BIG, bool BATCH, bool PIXEL>
+// Tuning (mapping only, never the moves): COMPACT for pixel phases, and
+// `remap` = 1 numbers the workgroups so that each XCD works a contiguous band.
+template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
-    uint32_t stamp, int replay_groups) {
-    phase_body<BIG, PIXEL ? 1 : 2>(
-        b, [&]() { return PhaseWork{resolve<BATCH>(b, one, map, level, cls), level, cls}; }, par,
-        pass, stamp, replay_groups);
+    uint32_t stamp, int replay_groups, int remap) {
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
+        b,
+        [&]() {
+            return PhaseWork{resolve<BATCH>(b, one, map, level, cls, remap), level, cls};
+        },
+        par, pass, stamp, replay_groups);
 }
 
 // A mixed launch: every item is one image at its own phase (level, class).
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
 template <bool BIG, bool PIXEL>
 __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base) {
-    phase_body<BIG, PIXEL ? 1 : 2>(
+    phase_body<BIG, PIXEL ? 1 : 2, true>(
         b,
         [&]() {
             const int lg = xcd_group();
@@ -164,15 +169,22 @@ __global__ __launch_bounds__(kPT) void k_descend(BatchArgs b, ImageDesc one, con
 
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
-                        int replay_groups, hipStream_t s) {
+                        int replay_groups, const PhaseTuning &tune, hipStream_t s) {
     const int lds = phase_lds_bytes(level, one.d.hs);
     const bool batch = b.nimg > 1;
-    auto fn = level == 0 ? (batch ? k_phase<false, true, true> : k_phase<false, false, true>)
-              : max_level >= 4
-                  ? (batch ? k_phase<true, true, false> : k_phase<true, false, false>)
-                  : (batch ? k_phase<false, true, false> : k_phase<false, false, false>);
+    decltype(&k_phase<false, false, true, true>) fn;
+    if (level == 0) {
+        if (tune.pixel_compact)
+            fn = batch ? k_phase<false, true, true, true> : k_phase<false, false, true, true>;
+        else
+            fn = batch ? k_phase<false, true, true, false> : k_phase<false, false, true, false>;
+    } else if (max_level >= 4) {
+        fn = batch ? k_phase<true, true, false, true> : k_phase<true, false, false, true>;
+    } else {
+        fn = batch ? k_phase<false, true, false, true> : k_phase<false, false, false, true>;
+    }
     hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, one, map, level, cls, par, pass,
-                       stamp, replay_groups);
+                       stamp, replay_groups, tune.xcd_remap ? 1 : 0);
     return hipGetLastError();
 }
 

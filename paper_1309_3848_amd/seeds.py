@@ -53,6 +53,10 @@ class seeds_server_stats(ctypes.Structure):
         "bytes_in_use", "peak_bytes_in_use", "budget_bytes")]
 
 
+class seeds_tuning(ctypes.Structure):
+    _fields_ = [("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
 class seeds_quality(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("pixels", "ue", "asa", "cue", "br_hits", "br_total")]
 
@@ -106,6 +110,10 @@ def lib() -> ctypes.CDLL:
             "seeds_server_poll": ([P, ctypes.POINTER(I64), I32, PI], S),
             "seeds_server_get_stats": ([P, ctypes.POINTER(seeds_server_stats)], S),
             "seeds_server_destroy": ([P], S),
+            "seeds_get_tuning": ([P, ctypes.POINTER(seeds_tuning)], S),
+            "seeds_set_tuning": ([P, ctypes.POINTER(seeds_tuning)], S),
+            "seeds_autotune": ([P, I32, ctypes.POINTER(seeds_tuning),
+                                ctypes.POINTER(ctypes.c_float), P], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -362,6 +370,27 @@ def seeds_server_get_stats(srv) -> dict:
 
 def seeds_server_destroy(srv) -> None:
     _check(lib().seeds_server_destroy(srv))
+
+
+def seeds_get_tuning(ctx) -> dict:
+    t = seeds_tuning()
+    _check(lib().seeds_get_tuning(ctx, ctypes.byref(t)))
+    return {"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap}
+
+
+def seeds_set_tuning(ctx, pixel_compaction: int = 1, xcd_remap: int = 1) -> None:
+    t = seeds_tuning(pixel_compaction, xcd_remap)
+    _check(lib().seeds_set_tuning(ctx, ctypes.byref(t)))
+
+
+def seeds_autotune(ctx, reps: int = 3, stream=None):
+    """Time the four launch mappings, keep the fastest; the context comes back
+    freshly initialised. Returns (chosen dict, medians in ms per variant)."""
+    t = seeds_tuning()
+    ms = (ctypes.c_float * 4)()
+    _check(lib().seeds_autotune(ctx, reps, ctypes.byref(t), ms, _stream(stream)))
+    return ({"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap},
+            [ms[i] for i in range(4)])
 
 
 def seeds_last_error() -> str:

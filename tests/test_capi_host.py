@@ -226,3 +226,11 @@ def test_server_without_a_device_reports_device_error(S):
     assert S.lib().seeds_server_create(ctypes.byref(srv), ctypes.byref(p), None) in (
         S.SEEDS_E_DEVICE, S.SEEDS_E_NOMEM)
     assert not srv.value
+
+
+def test_tuning_argument_checks(S):
+    L = S.lib()
+    t = S.seeds_tuning(1, 1)
+    assert L.seeds_get_tuning(None, ctypes.byref(t)) == S.SEEDS_E_INVAL
+    assert L.seeds_set_tuning(None, ctypes.byref(t)) == S.SEEDS_E_INVAL
+    assert L.seeds_autotune(None, 3, None, None, None) == S.SEEDS_E_INVAL
