@@ -277,3 +277,19 @@ def test_graph_replays(S, rule):
             del junk
     finally:
         S.seeds_destroy(ctx)
+
+
+@pytest.mark.parametrize("H,W,K,L", [(1024, 8191, 4000, 4), (8191, 1024, 3000, 3)])
+def test_largest_image(S, H, W, K, L):
+    """H * W just below the 2^23 limit, in both orientations."""
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(H, W, 300, 8.0, seed=77)
+    _compare(S, img, K=K, L=L, B=5, I=2, gamma=1, rule=0, check_valid=False)
+
+
+def test_image_at_the_limit_is_refused(S):
+    import torch
+    rgb = torch.zeros((2048, 4096, 3), dtype=torch.uint8, device="cuda")   # exactly 2^23 pixels
+    with pytest.raises(S.SeedsError) as e:
+        S.seeds_init(rgb, 1000, S.make_params(4, 5, 2, 1, 0))
+    assert e.value.status == S.SEEDS_E_INVAL

@@ -176,3 +176,18 @@ def test_submit_checks(S):
         assert done == [rid]
     finally:
         S.seeds_server_destroy(srv)
+
+
+def test_large_requests_in_the_mix(S):
+    """Serving sizes of the request trace (640x480, 1080p, 4K) at once."""
+    import torch
+    _say("serve large mix")
+    shapes = [(480, 640, 55, 153, 4), (1080, 1920, 377, 1036, 4), (2160, 3840, 1508, 4147, 4),
+              (480, 640, 55, 153, 4), (1080, 1920, 377, 1036, 4)]
+    imgs, reqs = _requests(shapes, seed0=1000)
+    got, stats = _serve(S, reqs, [0, 0, 3, 20, 60], _params(S, budget=2 << 30, I=4))
+    assert stats["peak_inflight"] >= 3
+    for i, (rgb, K, L) in enumerate(reqs):
+        assert np.array_equal(got[i], _solo(S, rgb, K, L, 5, 4, 1)), f"request {i} {shapes[i][:2]}"
+    ref, _, _ = oracle.seeds(imgs[0], 153, 4, 5, 4, 1, 0)
+    assert np.array_equal(got[0], ref)
