@@ -250,43 +250,22 @@ __device__ __forceinline__ void lds_bins(int j, int32_t *h, int &cnt, bool &firs
     }
 }
 
-// Sparse block histogram with wavefront ballots, for blocks of at most 64
-// pixels (one pixel per lane, segments of SEG lanes inside one wavefront):
-// for the lane's bin j (0xFF = no pixel), cnt = h_l(j) of its segment's block
-// and first = the lane is the lowest one of its segment with that bin. One
-// round per distinct bin in the wavefront; no LDS, no barrier.
+// Sparse block histogram for blocks of 4 pixels (one pixel per lane,
+// segments of SEG <= 4 lanes inside one wavefront): for the lane's bin j (0xFF
+// = no pixel), cnt = h_l(j) of its segment's block and first = the lane is
+// the lowest one of its segment with that bin. No LDS, no barrier.
 template <int SEG>
-__device__ __forceinline__ void ballot_bins(int j, int &cnt, bool &first) {
-    const int lane = threadIdx.x & 63;
-    if constexpr (SEG <= 16) {
-        // small segments: compare with each lane of the segment
-        const int me = lane & (SEG - 1);
-        cnt = 0;
-        first = j != 0xFF;
-#pragma unroll
-        for (int q = 0; q < SEG; ++q) {
-            const int v = __shfl(j, q, SEG);
-            const bool same = v == j && j != 0xFF;
-            cnt += same;
-            first = first && !(same && q < me);
-        }
-        return;
-    }
-    const uint64_t seg_mask =
-        (SEG == 64 ? ~0ull : ((1ull << SEG) - 1)) << ((lane / SEG) * SEG);
-    uint64_t todo = __ballot(j != 0xFF);
+__device__ __forceinline__ void shuffle_bins(int j, int &cnt, bool &first) {
+    static_assert(SEG <= 4, "larger segments count their bins in LDS (lds_bins)");
+    const int me = (threadIdx.x & 63) & (SEG - 1);
     cnt = 0;
-    first = false;
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int v = __shfl(j, leader);
-        const uint64_t same = __ballot(j == v);
-        if (j == v) {
-            const uint64_t mine = same & seg_mask;
-            cnt = __popcll(mine);
-            first = __ffsll((unsigned long long)mine) - 1 == lane;
-        }
-        todo &= ~same;
+    first = j != 0xFF;
+#pragma unroll
+    for (int q = 0; q < SEG; ++q) {
+        const int v = __shfl(j, q, SEG);
+        const bool same = v == j && j != 0xFF;
+        cnt += same;
+        first = first && !(same && q < me);
     }
 }
 
@@ -347,8 +326,8 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
             }
         }
         // The block's bins, whether or not the block turns out movable. Blocks of
-        // up to 64 pixels keep one bin per lane and group them with ballots;
-        // larger blocks are staged in LDS.
+        // up to 64 pixels keep one bin per lane and count them with shuffles (4
+        // pixels) or in an LDS row (16 and 64); larger blocks are staged in LDS.
         int j1 = 0xFF, cnt1 = 0;
         bool first1 = false;
         if constexpr (PPL == 1) {
@@ -357,7 +336,7 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
             if constexpr (kLdsBins)
                 lds_bins(j1, seg_hist, cnt1, first1);
             else
-                ballot_bins<SEG>(j1, cnt1, first1);
+                shuffle_bins<SEG>(j1, cnt1, first1);
         } else {
 #pragma unroll 4
             for (int tt = 0; tt < PPL; ++tt) {
