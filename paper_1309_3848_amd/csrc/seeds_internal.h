@@ -281,6 +281,10 @@ __host__ __device__ inline int zero_groups(const Dims &d) {
     return (int)((n + kZeroPerGroup - 1) / kZeroPerGroup);
 }
 
+// Copy n int32 from 16-byte-aligned device memory to device-visible pinned
+// host memory (dst is the device-side address) with a few workgroups.
+hipError_t launch_copy_out(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
+
 // Persistent cooperative refinement of a single image.
 hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,
                          const Sched &start, int max_phases, uint32_t stamp, hipStream_t s);

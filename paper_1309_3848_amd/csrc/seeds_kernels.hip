@@ -286,6 +286,24 @@ __global__ __launch_bounds__(kThreads) void k_expand(const int32_t *__restrict__
     if (x < W) out[(int64_t)y * W + x] = blab[(int64_t)(y >> level) * uw + (x >> level)];
 }
 
+// Labels out to pinned host memory through a narrow kernel: a few workgroups
+// stream the copy over PCIe while the rest of the device keeps refining. The
+// source is 16-byte aligned; the destination takes 16-byte stores when it is.
+__global__ __launch_bounds__(kThreads) void k_copy_out(int32_t *__restrict__ dst,
+                                                       const int32_t *__restrict__ src,
+                                                       int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    int64_t done = 0;
+    if (((uintptr_t)dst & 15) == 0) {
+        const int64_t n4 = n / 4;
+        for (int64_t k = i; k < n4; k += stride)
+            reinterpret_cast<int4 *>(dst)[k] = reinterpret_cast<const int4 *>(src)[k];
+        done = n4 * 4;
+    }
+    for (int64_t k = done + i; k < n; k += stride) dst[k] = src[k];
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -320,6 +338,12 @@ hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t
                          const int64_t *pitch_table, int groups, hipStream_t s) {
     hipLaunchKernelGGL(k_rehist, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one,
                        map, rgb_table, pitch_table);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s) {
+    constexpr int kCopyGroups = 16;
+    hipLaunchKernelGGL(k_copy_out, dim3(kCopyGroups), dim3(kThreads), 0, s, dst, src, n);
     return hipGetLastError();
 }
 

@@ -81,6 +81,7 @@ struct Request {
     Dims d;
     int32_t *out;
     bool out_host;
+    int32_t *out_dev;      // pinned host output as the device sees it, else nullptr
     ImageDesc g;
     Sched sc;
     size_t px_off, px_len, st_off, st_len;
@@ -350,6 +351,16 @@ seeds_status seeds_server_submit(seeds_server *sv, const uint8_t *rgb, int32_t H
     r->pitch = row_pitch_bytes;
     r->out = labels_out;
     r->out_host = out_is_host != 0;
+    r->out_dev = nullptr;
+    if (r->out_host) {
+        // pinned, device-visible host memory takes a narrow copy kernel;
+        // anything else (pageable memory) a plain asynchronous copy
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, labels_out) == hipSuccess &&
+            attr.type == hipMemoryTypeHost && attr.devicePointer)
+            r->out_dev = (int32_t *)attr.devicePointer;
+        (void)hipGetLastError();  // a pageable pointer leaves an error behind
+    }
     r->finish_tick = -1;
     r->reported = false;
     sv->queue.push_back(r);
@@ -529,9 +540,13 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     for (Request *r : finished_now) {
         if (e != hipSuccess) break;
         const size_t bytes = (size_t)r->d.H * r->d.W * 4;
-        e = hipMemcpyAsync(r->out, sv->ar.lab + r->g.lab, bytes,
-                           r->out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                           sv->copy);
+        if (r->out_dev)
+            e = launch_copy_out(r->out_dev, sv->ar.lab + r->g.lab, (int64_t)r->d.H * r->d.W,
+                                sv->copy);
+        else
+            e = hipMemcpyAsync(r->out, sv->ar.lab + r->g.lab, bytes,
+                               r->out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                               sv->copy);
         if (e == hipSuccess) e = hipEventRecord(r->done, sv->copy);
         r->finish_tick = t;
         sv->finishing.push_back(r);

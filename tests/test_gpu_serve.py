@@ -43,17 +43,19 @@ def _solo(S, rgb, K, L, B, I, gamma):
         S.seeds_destroy(ctx)
 
 
-def _serve(S, reqs, arrivals, params, host_out=False, max_ticks=100000):
+def _serve(S, reqs, arrivals, params, host_out=False, max_ticks=100000, pageable=()):
     """reqs: list of (rgb tensor, K, L); arrivals[i]: tick at which request i
     is submitted. Returns labels per request and the server stats."""
     import torch
     srv = S.seeds_server_create(params)
     outs, ids, done = [], {}, set()
     try:
-        for rgb, _, _ in reqs:
+        for i, (rgb, _, _) in enumerate(reqs):
             shape = tuple(rgb.shape[:2])
-            outs.append(torch.empty(shape, dtype=torch.int32, pin_memory=True) if host_out
-                        else torch.empty(shape, dtype=torch.int32, device="cuda"))
+            if host_out:
+                outs.append(torch.empty(shape, dtype=torch.int32, pin_memory=i not in pageable))
+            else:
+                outs.append(torch.empty(shape, dtype=torch.int32, device="cuda"))
         order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
         nxt, tick = 0, 0
         while len(done) < len(reqs):
@@ -106,7 +108,8 @@ def test_staggered_arrivals_match_solo_and_oracle(S):
 def test_host_outputs_and_simultaneous_arrivals(S):
     _say("serve host outputs")
     imgs, reqs = _requests(SHAPES, seed0=600)
-    got, _ = _serve(S, reqs, [0] * len(reqs), _params(S), host_out=True)
+    # pinned outputs take the copy kernel, pageable ones (1 and 4) a plain copy
+    got, _ = _serve(S, reqs, [0] * len(reqs), _params(S), host_out=True, pageable=(1, 4))
     for i, (rgb, K, L) in enumerate(reqs):
         assert np.array_equal(got[i], _solo(S, rgb, K, L, 5, 3, 1)), f"request {i}"
 
