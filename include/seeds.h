@@ -286,6 +286,8 @@ typedef struct {
                                  60% pixels (7 B per pixel), 8% histograms, 32%
                                  move logs                                         */
     int32_t max_inflight;     /* most images refined together, [1,65536]          */
+    int32_t pixel_compaction; /* launch mapping as in seeds_tuning (0 or 1)       */
+    int32_t xcd_remap;        /* (0 or 1); results do not depend on either        */
 } seeds_server_params;
 
 typedef struct {
@@ -294,7 +296,9 @@ typedef struct {
     int64_t bytes_in_use, peak_bytes_in_use, budget_bytes; /* pixels + histograms */
 } seeds_server_stats;
 
-/* B = 5, I = 4, gamma = 1, max_levels = 4, 4 GiB, 512 images.              */
+/* B = 5, I = 4, gamma = 1, max_levels = 4, 4 GiB, 512 images, no pixel
+ * compaction and hardware workgroup order (the faster mapping measured for
+ * mixed request traffic).                                                   */
 seeds_status seeds_server_default_params(seeds_server_params *p);
 
 /* Create a server whose ticks run on hip_stream; allocates the budget once.  */

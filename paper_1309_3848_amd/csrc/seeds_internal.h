@@ -268,7 +268,7 @@ hipError_t launch_quality(const int32_t *lab, const int32_t *gt, int H, int W, i
 // launch_phase; the launch's log slots start at slot_base.
 hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, bool pixel, int max_level,
                               int par, int groups, int replay_groups, int slot_base,
-                              hipStream_t s);
+                              const PhaseTuning &tune, hipStream_t s);
 hipError_t launch_descend_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s);
 // Zero both state copies of every item's image, then initialise it (quantise,
 // grid, histograms) from item.rgb.

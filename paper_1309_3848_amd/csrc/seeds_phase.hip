@@ -114,13 +114,13 @@ __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
 // Only the Prop. 1 rule (one pass per phase) runs this way. A tick runs its
 // pixel-level items and its block-level items as two launches of the two
 // kernel variants; the second takes the log slots after the first's.
-template <bool BIG, bool PIXEL>
+template <bool BIG, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase_mixed(
-    BatchArgs b, TickList l, int par, int replay_groups, int slot_base) {
-    phase_body<BIG, PIXEL ? 1 : 2, true>(
+    BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
         b,
         [&]() {
-            const int lg = xcd_group();
+            const int lg = remap ? xcd_group() : (int)blockIdx.x;
             const TickItem &it = l.items[find_tick_item(l, lg)];
             return PhaseWork{make_view(b, it.g, lg - it.first, it.groups), it.level, it.cls};
         },
@@ -190,11 +190,15 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
 
 hipError_t launch_phase_mixed(const BatchArgs &b, const TickList &l, bool pixel, int max_level,
                               int par, int groups, int replay_groups, int slot_base,
-                              hipStream_t s) {
+                              const PhaseTuning &tune, hipStream_t s) {
     const int lds = pixel ? 0 : phase_lds_bytes_upto(max_level, l.hs);
-    auto fn = pixel ? k_phase_mixed<false, true>
-                    : (max_level >= 4 ? k_phase_mixed<true, false> : k_phase_mixed<false, false>);
-    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups, slot_base);
+    decltype(&k_phase_mixed<false, true, true>) fn;
+    if (pixel)
+        fn = tune.pixel_compact ? k_phase_mixed<false, true, true> : k_phase_mixed<false, true, false>;
+    else
+        fn = max_level >= 4 ? k_phase_mixed<true, false, true> : k_phase_mixed<false, false, true>;
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, l, par, replay_groups, slot_base,
+                       tune.xcd_remap ? 1 : 0);
     return hipGetLastError();
 }
 

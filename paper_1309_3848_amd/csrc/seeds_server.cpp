@@ -110,6 +110,7 @@ int max_phase_groups(const Dims &d) {
 
 struct seeds_server {
     seeds_server_params p;
+    PhaseTuning tune;
     int device = 0;
     hipStream_t s = nullptr;
     hipStream_t copy = nullptr;    // label outputs, overlapped with the ticks
@@ -212,6 +213,8 @@ seeds_status seeds_server_default_params(seeds_server_params *p) {
     p->max_levels = 4;
     p->hbm_budget_bytes = (int64_t)4 << 30;
     p->max_inflight = 512;
+    p->pixel_compaction = 0;
+    p->xcd_remap = 0;
     return SEEDS_OK;
 }
 
@@ -232,9 +235,14 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
         return sfail(SEEDS_E_INVAL, "max_inflight %d outside [1,65536]", p->max_inflight);
     if (p->hbm_budget_bytes < ((int64_t)64 << 20) || p->hbm_budget_bytes > ((int64_t)128 << 30))
         return sfail(SEEDS_E_INVAL, "hbm_budget_bytes outside [64 MiB, 128 GiB]");
+    if ((p->pixel_compaction != 0 && p->pixel_compaction != 1) ||
+        (p->xcd_remap != 0 && p->xcd_remap != 1))
+        return sfail(SEEDS_E_INVAL, "pixel_compaction and xcd_remap are 0 or 1");
     seeds_server *sv = new (std::nothrow) seeds_server();
     if (!sv) return sfail(SEEDS_E_NOMEM, "host allocation failed");
     sv->p = *p;
+    sv->tune.pixel_compact = p->pixel_compaction != 0;
+    sv->tune.xcd_remap = p->xcd_remap != 0;
     sv->s = (hipStream_t)hip_stream;
     hipError_t e = hipGetDevice(&sv->device);
     // log entries per workgroup and phase: the most any level can produce
@@ -517,12 +525,13 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
             // the first launch of the tick adds the previous tick's deltas
             int replay = sv->prev_groups;
             if (pixel_groups > 0) {
-                e = launch_phase_mixed(b, pixel_l, true, 0, sv->par, pixel_groups, replay, 0, s);
+                e = launch_phase_mixed(b, pixel_l, true, 0, sv->par, pixel_groups, replay, 0,
+                                       sv->tune, s);
                 replay = 0;
             }
             if (e == hipSuccess && block_groups > 0)
                 e = launch_phase_mixed(b, block_l, false, max_level, sv->par, block_groups, replay,
-                                       pixel_groups, s);
+                                       pixel_groups, sv->tune, s);
             sv->prev_groups = phase_groups_total;
             sv->par ^= 1;
         } else if (sv->prev_groups > 0) {

@@ -44,7 +44,8 @@ SEEDS_MAX_BATCH = 4096
 class seeds_server_params(ctypes.Structure):
     _fields_ = [("bins_per_channel", ctypes.c_int32), ("iters_per_level", ctypes.c_int32),
                 ("gamma", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
 
 
 class seeds_server_stats(ctypes.Structure):
