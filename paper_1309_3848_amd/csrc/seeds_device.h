@@ -65,20 +65,32 @@ __device__ __forceinline__ Neighbourhood neighbourhood9(int k, int lN, int lNE, 
     return nb;
 }
 
-__device__ __forceinline__ Neighbourhood neighbourhood(const int32_t *__restrict__ units, int uw,
-                                                       int uh, int ux, int uy) {
+// Labels of a unit and its 8-ring on a unit grid (-1 outside), in the order
+// unit, N, NE, E, SE, S, SW, W, NW. Loading apart from the test lets a caller
+// issue other independent loads before it waits for these.
+struct Ring {
+    int l[9];
+};
+
+__device__ __forceinline__ Ring load_ring(const int32_t *__restrict__ units, int uw, int uh, int ux,
+                                          int uy) {
     const int64_t row = (int64_t)uy * uw;
     const bool hasN = uy > 0, hasS = uy + 1 < uh, hasW = ux > 0, hasE = ux + 1 < uw;
-    const int k = units[row + ux];
-    const int lN = hasN ? units[row - uw + ux] : -1;
-    const int lS = hasS ? units[row + uw + ux] : -1;
-    const int lW = hasW ? units[row + ux - 1] : -1;
-    const int lE = hasE ? units[row + ux + 1] : -1;
-    const int lNE = hasN && hasE ? units[row - uw + ux + 1] : -1;
-    const int lSE = hasS && hasE ? units[row + uw + ux + 1] : -1;
-    const int lSW = hasS && hasW ? units[row + uw + ux - 1] : -1;
-    const int lNW = hasN && hasW ? units[row - uw + ux - 1] : -1;
-    return neighbourhood9(k, lN, lNE, lE, lSE, lS, lSW, lW, lNW);
+    Ring r;
+    r.l[0] = units[row + ux];
+    r.l[1] = hasN ? units[row - uw + ux] : -1;
+    r.l[2] = hasN && hasE ? units[row - uw + ux + 1] : -1;
+    r.l[3] = hasE ? units[row + ux + 1] : -1;
+    r.l[4] = hasS && hasE ? units[row + uw + ux + 1] : -1;
+    r.l[5] = hasS ? units[row + uw + ux] : -1;
+    r.l[6] = hasS && hasW ? units[row + uw + ux - 1] : -1;
+    r.l[7] = hasW ? units[row + ux - 1] : -1;
+    r.l[8] = hasN && hasW ? units[row - uw + ux - 1] : -1;
+    return r;
+}
+
+__device__ __forceinline__ Neighbourhood neighbourhood(const Ring &r) {
+    return neighbourhood9(r.l[0], r.l[1], r.l[2], r.l[3], r.l[4], r.l[5], r.l[6], r.l[7], r.l[8]);
 }
 
 // Workgroups are dispatched round-robin over the eight XCDs (workgroup b runs
@@ -116,100 +128,84 @@ __device__ __forceinline__ int32_t segment_sum32(int32_t v) {
 // neighbours contain the cell; per axis that is
 // |([p-1, p+1] clipped to the image) n [q-1, q+1]| for cell coordinate q.
 __device__ __forceinline__ int axis_weight(int p, int q, int n) {
-    if (q < 0 || q >= n) return 0;
     const int lo = max(max(p - 1, 0), q - 1), hi = min(min(p + 1, n - 1), q + 1);
-    return hi >= lo ? hi - lo + 1 : 0;
+    return (q >= 0 && q < n) ? max(hi - lo + 1, 0) : 0;
 }
 
 
-// Pixel level, first test: is (x, y) a boundary pixel whose label stays
-// connected without it? Only the 3x3 neighbourhood is read.
-__device__ __forceinline__ bool pixel_movable(const Dims &d, const int32_t *__restrict__ lab, int x,
-                                              int y) {
-    int r3[3][3];
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int yy = y + dy, xx = x + dx;
-            r3[dy + 1][dx + 1] =
-                (yy >= 0 && yy < d.H && xx >= 0 && xx < d.W) ? lab[(int64_t)yy * d.W + xx] : -1;
-        }
-    return neighbourhood9(r3[1][1], r3[0][1], r3[0][2], r3[1][2], r3[2][2], r3[2][1], r3[2][0],
-                          r3[1][0], r3[0][0])
+// Pixel level, first test: is the pixel at the centre of window w (5x5
+// labels with row stride kWinW, -1 outside the image) a boundary pixel whose
+// label stays connected without it? Only the 3x3 neighbourhood is read.
+__device__ __forceinline__ bool pixel_movable(const int32_t *w) {
+    const int32_t *c = w + 2 * kWinW + 2;
+    return neighbourhood9(c[0], c[-kWinW], c[-kWinW + 1], c[1], c[kWinW + 1], c[kWinW],
+                          c[kWinW - 1], c[-1], c[-kWinW - 1])
         .movable;
 }
 
-// Pixel level decision for pixel (x, y) from the state in lab / hist:
-// best 4-neighbour label n of the gain
+// Pixel level decision for pixel (x, y) with colour bin j, from the 5x5
+// window w of labels around it (row stride kWinW, -1 outside the image; the
+// boundary term reads all of it, the rest only the 3x3 ring) and the
+// histograms hist: best 4-neighbour label n of the gain
 //   g = (h_n(j) - h_k(j) + 1) + gamma (W_n + |K_p| - W_k)
 // (colour part: Prop. 1 with one look-up per side; boundary part: Prop. 2),
 // ties to the smaller label, taken only if g > 0.
 struct PixelMove {
     int n;  // target label, -1 for no move
     int k;  // current label
-    int j;  // colour bin of the pixel
 };
 
-__device__ __forceinline__ PixelMove pixel_decision(const Dims &d, const int32_t *__restrict__ lab,
-                                                    const uint8_t *__restrict__ bins,
+__device__ __forceinline__ PixelMove pixel_decision(const Dims &d, const int32_t *w, int j,
                                                     const int32_t *__restrict__ hist, int x,
                                                     int y) {
     PixelMove mv;
     mv.n = -1;
-    // every label the decision needs, loaded at once (-1 outside the image):
-    // the 3x3 ring, and with the boundary term the whole 5x5 window
-    const int R = d.gamma ? 2 : 1;
-    int win[5][5];
-#pragma unroll
-    for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-            const int yy = y + dy, xx = x + dx;
-            const bool need = (dy >= -R && dy <= R && dx >= -R && dx <= R);
-            win[dy + 2][dx + 2] = (need && yy >= 0 && yy < d.H && xx >= 0 && xx < d.W)
-                                      ? lab[(int64_t)yy * d.W + xx]
-                                      : -1;
-        }
-    const int j = bins[(int64_t)y * d.W + x];
-    const Neighbourhood nb = neighbourhood9(win[2][2], win[1][2], win[1][3], win[2][3], win[3][3],
-                                            win[3][2], win[3][1], win[2][1], win[1][1]);
+    const int32_t *c = w + 2 * kWinW + 2;
+    const Neighbourhood nb = neighbourhood9(c[0], c[-kWinW], c[-kWinW + 1], c[1], c[kWinW + 1],
+                                            c[kWinW], c[kWinW - 1], c[-1], c[-kWinW - 1]);
     mv.k = nb.k;
-    mv.j = j;
     if (!nb.movable) return mv;
     const int k = nb.k;
     const int hk = hist[(int64_t)k * d.hs + j];
     int g[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-        g[c] = c < nb.nc ? hist[(int64_t)nb.cand[c] * d.hs + j] - hk + 1 : INT32_MIN / 2;
+    for (int q = 0; q < 4; ++q)
+        g[q] = q < nb.nc ? hist[(int64_t)nb.cand[q] * d.hs + j] - hk + 1 : INT32_MIN / 2;
     if (d.gamma) {
+        // row by row: per row, the sums of the column weights of the cells
+        // holding k and each candidate, then weighted by the row's weight
+        int wx[5];
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) wx[dx + 2] = axis_weight(x, x + dx, d.W);
         int wk = 0, wn[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int dy = -2; dy <= 2; ++dy) {
             const int wy = axis_weight(y, y + dy, d.H);
+            int rk = 0, rn[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int dx = -2; dx <= 2; ++dx) {
-                const int w = wy * axis_weight(x, x + dx, d.W);
-                const int l = win[dy + 2][dx + 2];
-                wk += l == k ? w : 0;
+                const int l = w[(dy + 2) * kWinW + dx + 2];
+                rk += l == k ? wx[dx + 2] : 0;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) wn[c] += l == nb.cand[c] ? w : 0;
+                for (int q = 0; q < 4; ++q) rn[q] += l == nb.cand[q] ? wx[dx + 2] : 0;
             }
+            wk += wy * rk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wn[q] += wy * rn[q];
         }
         const int kp = (min(x + 1, d.W - 1) - max(x - 1, 0) + 1) *
                        (min(y + 1, d.H - 1) - max(y - 1, 0) + 1);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nb.nc) g[c] += d.gamma * (wn[c] + kp - wk);
+        for (int q = 0; q < 4; ++q)
+            if (q < nb.nc) g[q] += d.gamma * (wn[q] + kp - wk);
     }
     // candidates are ascending, so a strict ">" keeps the smaller label on ties
     int bg = g[0], bn = nb.cand[0];
 #pragma unroll
-    for (int c = 1; c < 4; ++c)
-        if (c < nb.nc && g[c] > bg) {
-            bg = g[c];
-            bn = nb.cand[c];
+    for (int q = 1; q < 4; ++q)
+        if (q < nb.nc && g[q] > bg) {
+            bg = g[q];
+            bn = nb.cand[q];
         }
     mv.n = bg > 0 ? bn : -1;
     return mv;

@@ -179,18 +179,30 @@ __host__ __device__ inline int phase_lds_bytes_upto(int max_level, int hs) {
     return b;
 }
 
-// Units one workgroup of a phase launch handles at `level`, and workgroups an
-// image needs for one phase of class cls.
-__host__ __device__ inline int units_per_group(int level) {
-    return level == 0 ? kPersistentThreads : kPersistentThreads / seg_lanes(level);
+// Pixel phases work on tiles of kPixTX x kPixTY class pixels, one wavefront
+// per class row of the tile. A tile's pixels sit 3 apart, and their 5x5
+// windows together cover kWinH x kWinW image cells, which the workgroup
+// stages in LDS.
+constexpr int kPixTX = 64, kPixTY = kPersistentThreads / kPixTX;
+constexpr int kWinW = 3 * kPixTX + 2, kWinH = 3 * kPixTY + 2;
+__host__ __device__ inline int pixel_tiles_x(const Dims &d, int cls) {
+    return (class_cols(d.W, cls) + kPixTX - 1) / kPixTX;
 }
+__host__ __device__ inline int pixel_tiles(const Dims &d, int cls) {
+    return pixel_tiles_x(d, cls) * ((class_rows(d.H, cls) + kPixTY - 1) / kPixTY);
+}
+
+// Work items of one phase of class cls for an image (pixel tiles, or rounds of
+// kPersistentThreads / seg_lanes(level) blocks): one workgroup each in a
+// phase launch.
 __host__ __device__ inline int phase_groups(const Dims &d, int level, int cls) {
-    const int per = units_per_group(level);
+    if (level == 0) return pixel_tiles(d, cls);
+    const int per = kPersistentThreads / seg_lanes(level);
     return (class_units(d, level, cls) + per - 1) / per;
 }
 
-// Upper bound on the log entries (deltas) one workgroup produces in one round
-// of a phase at `level`.
+// Upper bound on the log entries (deltas) one workgroup produces in one work
+// item of a phase at `level`.
 __host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
     if (level == 0) return 2 * kPersistentThreads;
     const int segs = kPersistentThreads / seg_lanes(level);

@@ -70,7 +70,7 @@ template <bool BIG>
 __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
-    __shared__ PixelList pl;
+    __shared__ PixelTile pl;
     __shared__ int s_prev_n;
     const BatchArgs &b = a.b;
     const Dims &d = a.one.d;
@@ -139,20 +139,15 @@ PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu)
         occ < 1)
         occ = 1;
     int groups = cus * min(occ, max(1, groups_per_cu));
-    // no more groups than one round of the busiest level needs
+    // no more groups than the busiest phase has work items (class 0 is the
+    // largest class at every level)
     int useful = 1;
-    for (int l = 0; l < d.L; ++l) {
-        const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
-        const int n = class_cols(units_w(d, l), 0) * class_rows(units_h(d, l), 0);
-        useful = max(useful, (n + per_group - 1) / per_group);
-    }
+    for (int l = 0; l < d.L; ++l) useful = max(useful, phase_groups(d, l, 0));
     g.groups = max(1, min(groups, useful));
     int cap = 1;
     for (int l = 0; l < d.L; ++l) {
-        const int per_group = l == 0 ? kPT : kPT / seg_lanes(l);
-        const int n = class_cols(units_w(d, l), 0) * class_rows(units_h(d, l), 0);
-        const int rounds = (n + g.groups * per_group - 1) / (g.groups * per_group);
-        cap = max(cap, rounds * deltas_per_round(d, l));
+        const int items = (phase_groups(d, l, 0) + g.groups - 1) / g.groups;
+        cap = max(cap, items * deltas_per_round(d, l));
     }
     g.log_cap = cap;
     return g;

@@ -165,74 +165,109 @@ __device__ __forceinline__ void replay(const int2 *entries, int n, int32_t *W) {
 }
 
 // ---------------------------------------------------------------------------
-// Pixel phase, grid-stride over the pixels of the class. Most pixels are not
-// on a boundary, and a wavefront of neighbouring pixels nearly always holds
-// some that are: every thread first makes the cheap 3x3 test, the movable
-// pixels are packed into an LDS list (ballot + one LDS atomic per wavefront),
-// and dense wavefronts then evaluate the gains.
-struct PixelList {
+// Pixel phase, one tile of kPixTX x kPixTY class pixels per work item. The
+// pixels of a class sit 3 apart, so the 5x5 windows of a wavefront's pixels
+// overlap and a per-lane gather of each window cell would fetch every cache
+// line several times: the workgroup instead loads the tile's whole window
+// (kWinH x kWinW labels, -1 outside the image) into LDS with coalesced loads,
+// together with its pixels' bins, and reads every window from there.
+//
+// COMPACT: every thread first makes the cheap 3x3 test, the movable pixels
+// (~15%) are packed into a list (ballot + one LDS atomic per wavefront), and
+// dense wavefronts then evaluate the gains. Otherwise every thread decides its
+// own pixel. Both give the same moves.
+struct PixelTile {
+    int32_t lab[kWinH * kWinW];
     int n;
-    int unit[kPT];
+    int unit[kPT];  // packed list: thread | bin << 8
 };
 
-__device__ __forceinline__ void wave_append(PixelList &pl, bool take, int value) {
+__device__ __forceinline__ void wave_append(PixelTile &pt, bool take, int value) {
     const uint64_t m = __ballot(take);
     if (!m) return;
     const int lane = threadIdx.x & 63;
     int base = 0;
-    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(&pl.n, __popcll(m));
+    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(&pt.n, __popcll(m));
     base = __shfl(base, __ffsll((unsigned long long)m) - 1);
-    if (take) pl.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
+    if (take) pt.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
 }
 
-// COMPACT = false skips the pre-test: every thread decides its own pixel
-// (more arithmetic per wavefront, one dependent round of loads less). Both
-// give the same moves.
 template <bool COMPACT = true>
 __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int cls, int par,
-                                   DeltaTable &t, int2 *mylog, PixelList &pl) {
+                                   DeltaTable &t, int2 *mylog, PixelTile &pt) {
     const Dims &d = v.d;
+    const int cx = cls % 3, cy = cls / 3;
     const int ncx = class_cols(d.W, cls), ncy = class_rows(d.H, cls);
-    const int n = ncx * ncy;
+    const int ntx = (ncx + kPixTX - 1) / kPixTX;
+    const int ntiles = ntx * ((ncy + kPixTY - 1) / kPixTY);
     const int32_t *hR = pick(b.ar.state, par) + v.base;
     int32_t *W = pick(b.ar.state, par ^ 1);
-    const int per_round = v.ngroups * kPT;
-    const int rounds = (n + per_round - 1) / per_round;
-    const int grp = v.grp;
-    if constexpr (!COMPACT) {
-        for (int r = 0; r < rounds; ++r) {
-            const int i = r * per_round + grp * kPT + threadIdx.x;
-            if (i < n) {
-                const int x = cls % 3 + 3 * (i % ncx), y = cls / 3 + 3 * (i / ncx);
-                const PixelMove mv = pixel_decision(d, v.lab, v.bins, hR, x, y);
-                if (mv.n >= 0) {
-                    v.lab[(int64_t)y * d.W + x] = mv.n;
-                    table_add(b, t, W, mylog, (int32_t)(v.base + mv.n * d.hs + mv.j), 1);
-                    table_add(b, t, W, mylog, (int32_t)(v.base + mv.k * d.hs + mv.j), -1);
-                }
+    const int ci = threadIdx.x % kPixTX, cj = threadIdx.x / kPixTX;
+    static_assert(kWinW == 3 * kPixTX + 2 && 2 * kWinH <= 64 && kPT == 4 * kPixTX,
+                  "the window load covers 3 kPixTX + 2 columns with four wavefronts");
+    // one pixel's move: its label in place, its count from k to n
+    auto apply = [&](int x, int y, int j, const PixelMove &mv) {
+        v.lab[(int64_t)y * d.W + x] = mv.n;
+        table_add(b, t, W, mylog, (int32_t)(v.base + mv.n * d.hs + j), 1);
+        table_add(b, t, W, mylog, (int32_t)(v.base + mv.k * d.hs + j), -1);
+    };
+    for (int tile = v.grp; tile < ntiles; tile += v.ngroups) {
+        const int tx = tile % ntx, ty = tile / ntx;
+        const int x0 = cx + 3 * kPixTX * tx, y0 = cy + 3 * kPixTY * ty;  // first pixel
+        const int gi = tx * kPixTX + ci, gj = ty * kPixTY + cj;
+        const bool valid = gi < ncx && gj < ncy;
+        const int x = x0 + 3 * ci, y = y0 + 3 * cj;
+        // the bin and the window cells: independent loads, all in flight at once
+        const int j = valid ? v.bins[(int64_t)y * d.W + x] : 0xFF;
+        // Threads 0 .. 3 kPixTX - 1 load columns 0 .. 3 kPixTX - 1 of every window
+        // row, the last wavefront the two right-most columns (no division, so
+        // nothing per thread outlives the loads).
+        int cell[kWinH];
+        const bool wide = (int)threadIdx.x < 3 * kPixTX;
+        const int wl = (int)threadIdx.x - 3 * kPixTX;
+        const int wc = wide ? (int)threadIdx.x : 3 * kPixTX + (wl & 1);
+        const int wr = wide ? 0 : wl >> 1;
+        const int xx = x0 - 2 + wc;
+        const bool in_x = xx >= 0 && xx < d.W;
+        if (wide) {
+#pragma unroll
+            for (int r = 0; r < kWinH; ++r) {
+                const int yy = y0 - 2 + r;
+                cell[r] = (in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx] : -1;
+            }
+        } else {
+            const int yy = y0 - 2 + wr;
+            cell[0] = (wr < kWinH && in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx]
+                                                                   : -1;
+        }
+        __syncthreads();  // the previous tile's window and list are no longer read
+        if (wide) {
+#pragma unroll
+            for (int r = 0; r < kWinH; ++r) pt.lab[r * kWinW + wc] = cell[r];
+        } else if (wr < kWinH) {
+            pt.lab[wr * kWinW + wc] = cell[0];
+        }
+        if (threadIdx.x == 0) pt.n = 0;
+        __syncthreads();
+        if constexpr (!COMPACT) {
+            if (valid) {
+                const PixelMove mv =
+                    pixel_decision(d, pt.lab + 3 * cj * kWinW + 3 * ci, j, hR, x, y);
+                if (mv.n >= 0) apply(x, y, j, mv);
+            }
+        } else {
+            const bool take = valid && pixel_movable(pt.lab + 3 * cj * kWinW + 3 * ci);
+            wave_append(pt, take, (int)threadIdx.x | j << 8);
+            __syncthreads();
+            if ((int)threadIdx.x < pt.n) {
+                const int u = pt.unit[threadIdx.x];
+                const int ui = (u & 0xFF) % kPixTX, uj = (u & 0xFF) / kPixTX, uj_bin = u >> 8;
+                const int px = x0 + 3 * ui, py = y0 + 3 * uj;
+                const PixelMove mv =
+                    pixel_decision(d, pt.lab + 3 * uj * kWinW + 3 * ui, uj_bin, hR, px, py);
+                if (mv.n >= 0) apply(px, py, uj_bin, mv);
             }
         }
-        return;
-    }
-    for (int r = 0; r < rounds; ++r) {
-        if (threadIdx.x == 0) pl.n = 0;
-        __syncthreads();
-        const int i = r * per_round + grp * kPT + threadIdx.x;
-        bool take = false;
-        if (i < n) take = pixel_movable(d, v.lab, cls % 3 + 3 * (i % ncx), cls / 3 + 3 * (i / ncx));
-        wave_append(pl, take, i);
-        __syncthreads();
-        if ((int)threadIdx.x < pl.n) {
-            const int u = pl.unit[threadIdx.x];
-            const int x = cls % 3 + 3 * (u % ncx), y = cls / 3 + 3 * (u / ncx);
-            const PixelMove mv = pixel_decision(d, v.lab, v.bins, hR, x, y);
-            if (mv.n >= 0) {
-                v.lab[(int64_t)y * d.W + x] = mv.n;
-                table_add(b, t, W, mylog, (int32_t)(v.base + mv.n * d.hs + mv.j), 1);
-                table_add(b, t, W, mylog, (int32_t)(v.base + mv.k * d.hs + mv.j), -1);
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -313,31 +348,39 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         const int unit = (r * v.ngroups + grp) * SEGS + seg;
         const bool in_range = unit < nunits;
         int ux = 0, uy = 0;
+        if (in_range) {
+            ux = cls % 3 + 3 * (unit % ncx);
+            uy = cls / 3 + 3 * (unit / ncx);
+        }
+        // The block's bins and the labels around it are independent: both
+        // loads are issued before either is waited for, and blocks of up to 64
+        // pixels count their bins while the labels are still in flight.
+        int j1 = 0xFF, cnt1 = 0;
+        bool first1 = false;
+        if constexpr (PPL == 1) {
+            const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
+            j1 = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
+        }
         Neighbourhood nb;
         nb.movable = false;
         nb.k = -1;
         nb.nc = 0;
+        Ring ring;
         int target = -1;
         if (in_range) {
-            ux = cls % 3 + 3 * (unit % ncx);
-            uy = cls / 3 + 3 * (unit / ncx);
             if (pass == 2) {
                 target = v.pend[unit];
                 if (target >= 0 && v.src[target] == (int32_t)stamp) target = -1;
                 nb.movable = target >= 0;
                 nb.k = units[(int64_t)uy * uw + ux];
             } else {
-                nb = neighbourhood(units, uw, uh, ux, uy);
+                ring = load_ring(units, uw, uh, ux, uy);
             }
         }
-        // The block's bins, whether or not the block turns out movable. Blocks of
-        // up to 64 pixels keep one bin per lane and count them with shuffles (4
-        // pixels) or in an LDS row (16 and 64); larger blocks are staged in LDS.
-        int j1 = 0xFF, cnt1 = 0;
-        bool first1 = false;
+        // Blocks of up to 64 pixels keep one bin per lane and count them with
+        // shuffles (4 pixels) or in an LDS row (16 and 64); larger blocks are
+        // staged in LDS.
         if constexpr (PPL == 1) {
-            const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
-            j1 = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
             if constexpr (kLdsBins)
                 lds_bins(j1, seg_hist, cnt1, first1);
             else
@@ -351,6 +394,7 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
             }
             __syncthreads();
         }
+        if (in_range && pass != 2) nb = neighbourhood(ring);
         // pixel tt of this lane: its bin j and, if it is the first of its bin in
         // the block, the bin's count (0 otherwise)
         auto leader_bin = [&](int tt, int &j, int &cnt) {

@@ -41,7 +41,7 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
                                            int slot_base = 0) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
-    __shared__ PixelList pl;
+    __shared__ PixelTile pl;
     table_clear(t);
     __syncthreads();
     // The previous phase's deltas go to the copy this phase writes and nobody
@@ -99,7 +99,7 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
 // Tuning (mapping only, never the moves): COMPACT for pixel phases, and
 // `remap` = 1 numbers the workgroups so that each XCD works a contiguous band.
 template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT>
-__global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
+__global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
     uint32_t stamp, int replay_groups, int remap) {
     phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase(
 // pixel-level items and its block-level items as two launches of the two
 // kernel variants; the second takes the log slots after the first's.
 template <bool BIG, bool PIXEL, bool COMPACT>
-__global__ __launch_bounds__(kPT, (!PIXEL && !BIG) ? 6 : 1) void k_phase_mixed(
+__global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
     phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
         b,
