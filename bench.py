@@ -111,6 +111,25 @@ def measured_traffic():
     return t.get("traffic_bytes_per_launch")
 
 
+LDS_FILE = os.path.join(ROOT, "profiles", "k_phase_1080p_lds.json")
+# LDS atomics: one wavefront instruction of 64 32-bit lanes moves 256 B
+# through a CU's 128 B/clock LDS pipe, so at most one every two clocks per CU
+LDS_ATOMIC_PEAK_GINST = 256 * 2.4 / 2
+
+
+def measured_lds():
+    """LDS counters per phase launch from the committed rocprofv3 run, or None
+    when the kernel sources changed since."""
+    try:
+        with open(LDS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t
+
+
 def _percentiles(lat):
     lat = sorted(lat)
     return lat[len(lat) // 2], lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
@@ -777,6 +796,15 @@ def main() -> int:
     per_launch = refine_bytes / launches
     achieved = per_launch / (phase_us * 1e-6) / 1e9
     traffic = measured_traffic()
+    lds = measured_lds()
+    lds_atomics = None
+    if lds is not None:
+        per = lds["lds_atomic_insts_per_launch"]
+        rate = per / (phase_us * 1e-6) / 1e9
+        lds_atomics = {"achieved": round(rate, 3), "peak": LDS_ATOMIC_PEAK_GINST,
+                       "unit": "G wavefront-instructions/s", "frac": round(rate / LDS_ATOMIC_PEAK_GINST, 6),
+                       "per_launch": per, "bank_conflict_frac": lds["bank_conflict_frac"],
+                       "source": "profiles/k_phase_1080p_lds.json (rocprofv3 SQ_INSTS_LDS_ATOMIC)"}
     gpu_labels = out.cpu().numpy()
     S.seeds_destroy(ctx)
 
@@ -801,6 +829,7 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "launches_per_image": launches, "avg_launch_us": round(phase_us, 3),
                      "refine_ms": round(refine_ms, 4)},
+        "lds_atomics": lds_atomics,
     }
 
     if not args.no_cpu_baseline:
