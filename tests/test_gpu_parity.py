@@ -140,6 +140,41 @@ def test_edge_shapes(S, H, W, K, L, mode):
     _compare(S, img, K, L, B=5, I=3, gamma=1, mode=mode)
 
 
+@pytest.mark.parametrize("compaction", [1, 0])
+@pytest.mark.parametrize("H,W", [
+    (11, 189), (12, 190), (13, 191), (14, 192), (15, 193), (24, 194), (25, 195), (26, 196),
+    (37, 383), (12, 384), (13, 385), (5, 577), (190, 14),
+])
+def test_pixel_tile_edges(S, H, W, compaction):
+    """Pixel phases work on tiles of 64 x 4 class pixels (192 x 12 image pixels of
+    one class, plus a 2-pixel window margin): shapes on both sides of the tile
+    and window edges, with and without the compaction of movable pixels."""
+    import torch
+    from paper_1309_3848_amd import synth
+    img = synth.voronoi_image(H, W, 9, 8.0, seed=H * 7919 + W)
+    for K, L in ((6, 1), (12, 2)):
+        _say(f"tile edges shape={H}x{W} K={K} L={L} compaction={compaction}")
+        rgb = torch.from_numpy(img).cuda()
+        ctx = S.seeds_init(rgb, K, S.make_params(L, 5, 3, 1, 0))
+        try:
+            S.seeds_set_tuning(ctx, compaction, 1)
+            S.seeds_refine(ctx)
+            lab = torch.empty((H, W), dtype=torch.int32, device="cuda")
+            S.seeds_labels(ctx, lab)
+            keff = S.seeds_num_superpixels(ctx)
+            hist = torch.empty((keff, 125), dtype=torch.int32)
+            size = torch.empty((keff,), dtype=torch.int32)
+            S.seeds_histograms(ctx, hist, size)
+            S.seeds_sync(ctx)
+        finally:
+            S.seeds_destroy(ctx)
+        ref_lab, ref_hist, ref_size = oracle.seeds(img, K, L, 5, 3, 1, 0)
+        bad = np.argwhere(lab.cpu().numpy() != ref_lab)
+        assert bad.size == 0, f"{len(bad)} labels differ, first at {bad[:5].tolist()}"
+        assert np.array_equal(hist.numpy(), ref_hist)
+        assert np.array_equal(size.numpy(), ref_size)
+
+
 def test_flat_and_two_colour_images(S, mode):
     img = np.full((64, 96, 3), 140, np.uint8)
     _compare(S, img, 24, 4, 5, 3, 0, mode=mode)
