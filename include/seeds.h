@@ -138,6 +138,18 @@ seeds_status seeds_histograms(const seeds_ctx *ctx, int32_t *hist, int32_t *size
 /* Test hook: current level of the context (0 = pixel level) or -1 for NULL.   */
 int32_t seeds_level(const seeds_ctx *ctx);
 
+/* Test hook: the energies of the current state in count form (Sec. 4), as
+ * exact 64-bit integers written to host memory:
+ *   *h_energy = H' = sum_k sum_j h_k(j)^2 over the colour histograms;
+ *   *g_energy = G' = sum_i sum_k b_i(k)^2, b_i(k) the number of pixels of
+ *               label k in the 3x3 patch around pixel i (clipped at the image
+ *               border), on the pixel labels seeds_labels would return.
+ * Hill climbing with the exact block rule never lowers H' at block levels,
+ * nor H' + gamma G' at pixel level. SEEDS_E_INVAL for NULL outputs; the call
+ * allocates a little device memory in stream order and waits for the stream. */
+seeds_status seeds_energy(const seeds_ctx *ctx, int64_t *h_energy, int64_t *g_energy,
+                          void *hip_stream);
+
 typedef enum {
     SEEDS_LAUNCH_GRAPH = 0,      /* default: one kernel per phase, the launches of a
                                     whole refine call captured once into a HIP
@@ -255,13 +267,16 @@ seeds_status seeds_batch_warm_start(seeds_ctx *ctx, const uint8_t *const *rgb,
 /* Number of images of the context (1 for seeds_init contexts; -1 for NULL). */
 int32_t seeds_batch_count(const seeds_ctx *ctx);
 
-/* seeds_labels, seeds_histograms and seeds_num_superpixels for image `image`
- * of the context (SEEDS_E_INVAL, or -1, when the index is out of range).    */
+/* seeds_labels, seeds_histograms, seeds_num_superpixels and seeds_energy for
+ * image `image` of the context (SEEDS_E_INVAL, or -1, when the index is out of
+ * range).                                                                    */
 seeds_status seeds_batch_labels(const seeds_ctx *ctx, int32_t image, int32_t *out,
                                 int32_t out_is_host, void *hip_stream);
 seeds_status seeds_batch_histograms(const seeds_ctx *ctx, int32_t image, int32_t *hist,
                                     int32_t *size, int32_t out_is_host, void *hip_stream);
 int32_t seeds_batch_num_superpixels(const seeds_ctx *ctx, int32_t image);
+seeds_status seeds_batch_energy(const seeds_ctx *ctx, int32_t image, int64_t *h_energy,
+                                int64_t *g_energy, void *hip_stream);
 
 /* ---- Serving -------------------------------------------------------------
  * A request loop with continuous batching. Requests (images on the device)

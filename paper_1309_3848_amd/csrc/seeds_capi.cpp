@@ -632,6 +632,36 @@ seeds_status histograms_of(seeds_ctx *ctx, int32_t image, int32_t *hist, int32_t
     return SEEDS_OK;
 }
 
+// H' and G' of one image's current state (G' on the pixel labels that
+// labels_of returns); host outputs, waits for the stream.
+seeds_status energy_of(seeds_ctx *ctx, int32_t image, int64_t *h_energy, int64_t *g_energy,
+                       hipStream_t s) {
+    const ImageDesc &g = ctx->imgs[image];
+    const Dims &d = g.d;
+    const int level = image_level(ctx, image);
+    const size_t lab_bytes = level == 0 ? 0 : (size_t)d.H * d.W * 4;
+    void *buf = nullptr;
+    hipError_t e = hipMallocAsync(&buf, 16 + lab_bytes, s);
+    if (e != hipSuccess) return device_error(nullptr, e, "hipMallocAsync");
+    unsigned long long *cnt = (unsigned long long *)buf;
+    const int32_t *lab = ctx->ar.lab + g.lab;
+    if (level > 0) {
+        int32_t *pix = (int32_t *)((char *)buf + 16);
+        e = launch_expand(d, image_units(ctx, image), level, pix, s);
+        lab = pix;
+    }
+    unsigned long long host[2] = {0, 0};
+    if (e == hipSuccess) e = launch_energy(ctx->ar.state[0] + g.state, d, lab, cnt, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, cnt, 16, hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipFreeAsync(buf, s);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(ctx, e, "energy");
+    *h_energy = (int64_t)host[0];
+    *g_energy = (int64_t)host[1];
+    return check_device_flag(ctx, s);
+}
+
 // Take new image pointers and pitches (checked) for the next init or warm
 // start. A batch keeps them in device tables, re-uploaded only on change.
 seeds_status set_images(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t *row_pitch_bytes,
@@ -849,6 +879,20 @@ seeds_status seeds_batch_histograms(const seeds_ctx *cctx, int32_t image, int32_
     seeds_status st = check_image(ctx, image);
     if (st != SEEDS_OK) return st;
     return histograms_of(ctx, image, hist, size, out_is_host, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_energy(const seeds_ctx *ctx, int64_t *h_energy, int64_t *g_energy,
+                          void *hip_stream) {
+    return seeds_batch_energy(ctx, 0, h_energy, g_energy, hip_stream);
+}
+
+seeds_status seeds_batch_energy(const seeds_ctx *cctx, int32_t image, int64_t *h_energy,
+                                int64_t *g_energy, void *hip_stream) {
+    seeds_ctx *ctx = const_cast<seeds_ctx *>(cctx);
+    seeds_status st = check_image(ctx, image);
+    if (st != SEEDS_OK) return st;
+    if (!h_energy || !g_energy) return fail(SEEDS_E_INVAL, "energy outputs are NULL");
+    return energy_of(ctx, image, h_energy, g_energy, (hipStream_t)hip_stream);
 }
 
 seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode) {

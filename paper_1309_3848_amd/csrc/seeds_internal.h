@@ -293,6 +293,12 @@ __host__ __device__ inline int zero_groups(const Dims &d) {
     return (int)((n + kZeroPerGroup - 1) / kZeroPerGroup);
 }
 
+// Test hook: out[0] = H' (sum of squared histogram cells of one image, row
+// stride d.hs) and out[1] = G' (sum over pixels of the squared label counts of
+// their clipped 3x3 patches) of H x W labels; out (two counters) is zeroed here.
+hipError_t launch_energy(const int32_t *hist, const Dims &d, const int32_t *lab,
+                         unsigned long long *out, hipStream_t s);
+
 // Copy n int32 from 16-byte-aligned device memory to device-visible pinned
 // host memory (dst is the device-side address) with a few workgroups.
 hipError_t launch_copy_out(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);

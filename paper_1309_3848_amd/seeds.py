@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
             "seeds_batch_labels": ([P, I32, P, I32, P], S),
             "seeds_batch_histograms": ([P, I32, P, P, I32, P], S),
             "seeds_batch_num_superpixels": ([P, I32], I32),
+            "seeds_energy": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
+            "seeds_batch_energy": ([P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
             "seeds_quality_metrics": ([P, P, I32, I32, I32, I32, I32, ctypes.POINTER(seeds_quality),
                                        P], S),
             "seeds_server_default_params": ([ctypes.POINTER(seeds_server_params)], S),
@@ -293,6 +295,19 @@ def seeds_histograms(ctx, hist: torch.Tensor | None, size: torch.Tensor | None, 
                                   size.data_ptr() if size is not None else None,
                                   1 if host else 0, _stream(stream)))
     return hist, size
+
+
+def seeds_energy(ctx, stream=None) -> tuple:
+    """(H', G') of the context's state in count form (exact integers)."""
+    h, g = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().seeds_energy(ctx, ctypes.byref(h), ctypes.byref(g), _stream(stream)))
+    return h.value, g.value
+
+
+def seeds_batch_energy(ctx, image: int, stream=None) -> tuple:
+    h, g = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().seeds_batch_energy(ctx, image, ctypes.byref(h), ctypes.byref(g), _stream(stream)))
+    return h.value, g.value
 
 
 def seeds_set_launch_mode(ctx, mode: int) -> None:

@@ -10,7 +10,7 @@ import pytest
 
 from paper_1309_3848_amd import build as hipbuild
 
-HOT = ["seeds_phase.hip", "seeds_kernels.hip", "seeds_quality.hip"]
+HOT = ["seeds_phase.hip", "seeds_kernels.hip", "seeds_quality.hip", "seeds_energy.hip"]
 
 
 def _usage(src):
@@ -29,5 +29,5 @@ def _usage(src):
 @pytest.mark.parametrize("src", HOT)
 def test_hot_kernels_use_no_scratch(src):
     usage = _usage(src)
-    assert any(k in n for n in usage for k in ("k_phase", "k_init", "k_q_count"))
+    assert any(k in n for n in usage for k in ("k_phase", "k_init", "k_q_count", "k_energy"))
     assert {n: s for n, s in usage.items() if s} == {}
