@@ -176,7 +176,7 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  *   xcd_remap         1: workgroups are numbered so that each of the eight
  *                     XCDs works a contiguous band of the image (fewer L2
  *                     misses); 0: hardware order.
- * Default: both 1.                                                           */
+ * Default: pixel_compaction 0, xcd_remap 1.                                  */
 typedef struct {
     int32_t pixel_compaction;
     int32_t xcd_remap;

@@ -244,7 +244,7 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
 // max_level: the largest level of any image (selects the kernel variant).
 // Mapping choices of the per-phase launches (results never depend on them).
 struct PhaseTuning {
-    bool pixel_compact = true;  // pixel phases: pre-test and compaction
+    bool pixel_compact = false;  // pixel phases: pre-test and compaction
     bool xcd_remap = true;      // workgroups numbered in contiguous bands per XCD
 };
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,

@@ -217,28 +217,54 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
         const int gi = tx * kPixTX + ci, gj = ty * kPixTY + cj;
         const bool valid = gi < ncx && gj < ncy;
         const int x = x0 + 3 * ci, y = y0 + 3 * cj;
-        // the bin and the window cells: independent loads, all in flight at once
-        const int j = valid ? v.bins[(int64_t)y * d.W + x] : 0xFF;
-        // Threads 0 .. 3 kPixTX - 1 load columns 0 .. 3 kPixTX - 1 of every window
-        // row, the last wavefront the two right-most columns (no division, so
-        // nothing per thread outlives the loads).
+        // The bin and the window cells: independent loads, all in flight at
+        // once. Threads 0 .. 3 kPixTX - 1 load columns 0 .. 3 kPixTX - 1 of every
+        // window row, the last wavefront the two right-most columns (no
+        // division, so nothing per thread outlives the loads).
         int cell[kWinH];
+        int j;
         const bool wide = (int)threadIdx.x < 3 * kPixTX;
         const int wl = (int)threadIdx.x - 3 * kPixTX;
         const int wc = wide ? (int)threadIdx.x : 3 * kPixTX + (wl & 1);
         const int wr = wide ? 0 : wl >> 1;
         const int xx = x0 - 2 + wc;
         const bool in_x = xx >= 0 && xx < d.W;
-        if (wide) {
+        if constexpr (!COMPACT) {
+            // Unconditional loads from addresses clamped into the image, with
+            // out-of-image cells replaced afterwards: a load behind a branch,
+            // or into a register preset to a default, is waited for (with every
+            // load before it) at the end of its branch. (The compacting variant
+            // keeps the branches: it has no registers to spare for this form.)
+            j = v.bins[(int64_t)min(y, d.H - 1) * d.W + min(x, d.W - 1)];
+            const int xc = min(max(xx, 0), d.W - 1);
+            if (wide) {
 #pragma unroll
-            for (int r = 0; r < kWinH; ++r) {
-                const int yy = y0 - 2 + r;
-                cell[r] = (in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx] : -1;
+                for (int r = 0; r < kWinH; ++r)
+                    cell[r] = v.lab[(int64_t)min(max(y0 - 2 + r, 0), d.H - 1) * d.W + xc];
+#pragma unroll
+                for (int r = 0; r < kWinH; ++r) {
+                    const int yy = y0 - 2 + r;
+                    if (!(in_x && yy >= 0 && yy < d.H)) cell[r] = -1;
+                }
+            } else {
+                const int yy = y0 - 2 + min(wr, kWinH - 1);
+                cell[0] = v.lab[(int64_t)min(max(yy, 0), d.H - 1) * d.W + xc];
+                if (!(in_x && yy >= 0 && yy < d.H)) cell[0] = -1;
             }
         } else {
-            const int yy = y0 - 2 + wr;
-            cell[0] = (wr < kWinH && in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx]
-                                                                   : -1;
+            j = valid ? v.bins[(int64_t)y * d.W + x] : 0xFF;
+            if (wide) {
+#pragma unroll
+                for (int r = 0; r < kWinH; ++r) {
+                    const int yy = y0 - 2 + r;
+                    cell[r] = (in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx] : -1;
+                }
+            } else {
+                const int yy = y0 - 2 + wr;
+                cell[0] = (wr < kWinH && in_x && yy >= 0 && yy < d.H)
+                              ? v.lab[(int64_t)yy * d.W + xx]
+                              : -1;
+            }
         }
         __syncthreads();  // the previous tile's window and list are no longer read
         if (wide) {

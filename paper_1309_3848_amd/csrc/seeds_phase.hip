@@ -51,14 +51,11 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     // end; a longer log (rare) is read once its length is known.
     int32_t *W = pick(b.ar.state, par ^ 1);
     constexpr int kPre = 64;
-    int2 pre = make_int2(0, 0);
-    int pre_n = 0;
+    // (unconditional loads: the slot exists whatever replay_groups is)
     const bool replay_own = (int)blockIdx.x < replay_groups;
     const int64_t own_slot = (int64_t)(par ^ 1) * b.log_groups + blockIdx.x;
-    if (replay_own) {
-        pre_n = b.ar.log_n[own_slot];
-        if (threadIdx.x < kPre) pre = b.ar.log[own_slot * b.log_cap + threadIdx.x];
-    }
+    const int pre_n = replay_own ? b.ar.log_n[own_slot] : 0;
+    const int2 pre = b.ar.log[own_slot * b.log_cap + (threadIdx.x & (kPre - 1))];
     const PhaseWork w = find();
     // this workgroup's log slot: a phase split over two launches gives the
     // second one the slots after the first one's

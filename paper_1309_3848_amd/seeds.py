@@ -394,7 +394,7 @@ def seeds_get_tuning(ctx) -> dict:
     return {"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap}
 
 
-def seeds_set_tuning(ctx, pixel_compaction: int = 1, xcd_remap: int = 1) -> None:
+def seeds_set_tuning(ctx, pixel_compaction: int = 0, xcd_remap: int = 1) -> None:
     t = seeds_tuning(pixel_compaction, xcd_remap)
     _check(lib().seeds_set_tuning(ctx, ctypes.byref(t)))
 
