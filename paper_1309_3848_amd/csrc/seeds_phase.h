@@ -446,30 +446,39 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
             const int64_t m = (int64_t)min(s, d.W - ux * s) * min(s, d.H - uy * s);
             if (pass != 2) {
                 // evaluate the candidates: every pixel that is the first of its
-                // bin in the block contributes for its bin j with count h_l(j)
-                const int64_t Ak = sR[k];
-                int64_t An[4] = {0, 0, 0, 0};
+                // bin in the block contributes for its bin j with count h_l(j).
+                // Every lane loads the sizes and its cells, unused candidates
+                // and non-leading lanes at valid stand-in indices: a load behind
+                // a branch is waited for at the end of that branch, which would
+                // make each candidate's loads a memory round trip of their own.
+                int cs[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (c < nb.nc) An[c] = sR[nb.cand[c]];
+                for (int c = 0; c < 4; ++c) cs[c] = c < nb.nc ? nb.cand[c] : k;
+                const int64_t Ak = sR[k];
+                int64_t An[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) An[c] = sR[cs[c]];
                 int64_t acc[4] = {0, 0, 0, 0}, acc_kl = 0;
 #pragma unroll 4
                 for (int tt = 0; tt < PPL; ++tt) {
                     int j, cnt;
                     leader_bin(tt, j, cnt);
+                    const int js = j == 0xFF ? 0 : j;
+                    const int64_t hk = hR[(int64_t)k * d.hs + js];
+                    int64_t hn[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) hn[c] = hR[(int64_t)cs[c] * d.hs + js];
                     if (!cnt) continue;
                     const int64_t hl = cnt;
-                    const int64_t hk = hR[(int64_t)k * d.hs + j];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         if (c >= nb.nc) break;
-                        const int64_t hn = hR[(int64_t)nb.cand[c] * d.hs + j];
                         if (exact) {
                             // EXACT: h_l(j) (h_n(j) - h_k(j) + h_l(j))
-                            acc[c] += hl * (hn - hk + hl);
+                            acc[c] += hl * (hn[c] - hk + hl);
                         } else {
                             // Prop. 1: min(h_n(j) m, h_l(j) A_n)
-                            const int64_t x1 = hn * m, x2 = hl * An[c];
+                            const int64_t x1 = hn[c] * m, x2 = hl * An[c];
                             acc[c] += x1 < x2 ? x1 : x2;
                         }
                     }
