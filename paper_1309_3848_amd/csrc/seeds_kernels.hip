@@ -58,12 +58,24 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         for (int i = threadIdx.x; i < nslots; i += kThreads) sl.size[i] = 0;
     }
     __syncthreads();
-    const int x = x0 + (int)(threadIdx.x % kInitTW);
-    for (int r = threadIdx.x / kInitTW; r < kInitTH; r += kThreads / kInitTW) {
-        const int y = y0 + r;
+    // every pixel's colour is loaded first, from addresses clamped into the
+    // image (a load behind a branch is waited for at the end of the branch)
+    constexpr int kRows = kInitTH * kInitTW / kThreads;
+    const int x = x0 + (int)(threadIdx.x % kInitTW), xc = min(x, d.W - 1);
+    uint8_t c0[kRows], c1[kRows], c2[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int yc = min(y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW), d.H - 1);
+        const uint8_t *p = rgb + (int64_t)yc * pitch + 3 * (int64_t)xc;
+        c0[q] = p[0];
+        c1[q] = p[1];
+        c2[q] = p[2];
+    }
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
         if (x >= d.W || y >= d.H) continue;
-        const uint8_t *p = rgb + (int64_t)y * pitch + 3 * (int64_t)x;
-        const int j = (((p[0] * d.B) >> 8) * d.B + ((p[1] * d.B) >> 8)) * d.B + ((p[2] * d.B) >> 8);
+        const int j = (((c0[q] * d.B) >> 8) * d.B + ((c1[q] * d.B) >> 8)) * d.B + ((c2[q] * d.B) >> 8);
         bins[(int64_t)y * d.W + x] = (uint8_t)j;
         const int sx = grid_col(x, d, bw), sy = grid_row(y, d, bh);
         const int label = sy * d.gx + sx;
@@ -194,20 +206,32 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
     }
     if (threadIdx.x == 0) r.nslots = 0;
     __syncthreads();
-    // the thread's pixels: bins (written now) and labels, kept in registers
+    // the thread's pixels: bins (written now) and labels, kept in registers.
+    // Every pixel's loads go out first, from addresses clamped into the image
+    // (a load behind a branch is waited for at the end of the branch).
     int32_t k[kRehistPx], j[kRehistPx];
-    const int x = x0 + (int)(threadIdx.x % kInitTW);
+    uint8_t c0[kRehistPx], c1[kRehistPx], c2[kRehistPx];
+    const int x = x0 + (int)(threadIdx.x % kInitTW), xc = min(x, d.W - 1);
 #pragma unroll
     for (int q = 0; q < kRehistPx; ++q) {
         const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
-        k[q] = -1;
+        const int yc = min(y, d.H - 1);
+        const uint8_t *p = rgb + (int64_t)yc * pitch + 3 * (int64_t)xc;
+        c0[q] = p[0];
+        c1[q] = p[1];
+        c2[q] = p[2];
+        k[q] = lab[(int64_t)yc * d.W + xc];
+    }
+#pragma unroll
+    for (int q = 0; q < kRehistPx; ++q) {
+        const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
         j[q] = 0;
         if (x < d.W && y < d.H) {
-            const uint8_t *p = rgb + (int64_t)y * pitch + 3 * (int64_t)x;
-            j[q] = (((p[0] * d.B) >> 8) * d.B + ((p[1] * d.B) >> 8)) * d.B + ((p[2] * d.B) >> 8);
+            j[q] = (((c0[q] * d.B) >> 8) * d.B + ((c1[q] * d.B) >> 8)) * d.B + ((c2[q] * d.B) >> 8);
             bins[(int64_t)y * d.W + x] = (uint8_t)j[q];
-            k[q] = lab[(int64_t)y * d.W + x];
             rehist_entry(r, k[q], true);
+        } else {
+            k[q] = -1;
         }
     }
     __syncthreads();
