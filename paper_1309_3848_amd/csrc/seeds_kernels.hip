@@ -33,8 +33,11 @@ __device__ __forceinline__ int grid_row(int y, const Dims &d, int bh) {
     return (int)(((int64_t)(y / d.T) * d.gy) / bh);
 }
 
+// The slots' histograms (kMaxSlots x hs) live in dynamic LDS sized for the
+// launch's row stride, so that small histograms leave room for more
+// workgroups per CU.
+extern __shared__ int32_t dyn_hist[];
 struct InitSlots {
-    int32_t hist[kMaxSlots * kMaxHs];
     int32_t size[kMaxSlots];
 };
 
@@ -54,7 +57,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     const int nslots = nsx * (sy_hi - sy_lo + 1);
     const bool local = nslots <= kMaxSlots;
     if (local) {
-        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) sl.hist[i] = 0;
+        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) dyn_hist[i] = 0;
         for (int i = threadIdx.x; i < nslots; i += kThreads) sl.size[i] = 0;
     }
     __syncthreads();
@@ -82,7 +85,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         if (x % d.T == 0 && y % d.T == 0) top[(int64_t)(y / d.T) * bw + x / d.T] = label;
         if (local) {
             const int slot = (sy - sy_lo) * nsx + (sx - sx_lo);
-            atomicAdd(&sl.hist[slot * d.hs + j], 1);
+            atomicAdd(&dyn_hist[slot * d.hs + j], 1);
             atomicAdd(&sl.size[slot], 1);
         } else {
             atomicAdd(&st0[(int64_t)label * d.hs + j], 1);
@@ -94,7 +97,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     __syncthreads();
     if (!local) return;
     for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) {
-        const int v = sl.hist[i];
+        const int v = dyn_hist[i];
         if (!v) continue;
         const int slot = i / d.hs, j = i - slot * d.hs;
         const int label = (sy_lo + slot / nsx) * d.gx + sx_lo + slot % nsx;
@@ -173,8 +176,7 @@ constexpr int kRehistKeys = 64, kRehistSlots = 32;
 struct RehistLds {
     int32_t key[kRehistKeys];   // label, or -1
     int32_t slot[kRehistKeys];  // histogram slot of the label, or -1 (global)
-    int32_t nslots;
-    int32_t hist[kRehistSlots * kMaxHs];
+    int32_t nslots;  // histograms: kRehistSlots x hs in dynamic LDS (dyn_hist)
     int32_t size[kRehistSlots];
     int32_t label[kRehistSlots];
 };
@@ -246,7 +248,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
     }
     __syncthreads();
     const int ns = min(r.nslots, kRehistSlots);
-    for (int i = threadIdx.x; i < ns * d.hs; i += kThreads) r.hist[i] = 0;
+    for (int i = threadIdx.x; i < ns * d.hs; i += kThreads) dyn_hist[i] = 0;
     for (int i = threadIdx.x; i < ns; i += kThreads) r.size[i] = 0;
     __syncthreads();
 #pragma unroll
@@ -255,7 +257,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         const int e = rehist_entry(r, k[q], false);
         const int s = e >= 0 ? r.slot[e] : -1;
         if (s >= 0) {
-            atomicAdd(&r.hist[s * d.hs + j[q]], 1);
+            atomicAdd(&dyn_hist[s * d.hs + j[q]], 1);
             atomicAdd(&r.size[s], 1);
         } else {
             atomicAdd(&st0[(int64_t)k[q] * d.hs + j[q]], 1);
@@ -266,7 +268,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
     }
     __syncthreads();
     for (int i = threadIdx.x; i < ns * d.hs; i += kThreads) {
-        const int v = r.hist[i];
+        const int v = dyn_hist[i];
         if (!v) continue;
         const int s = i / d.hs, jj = i - s * d.hs;
         atomicAdd(&st0[(int64_t)r.label[s] * d.hs + jj], v);
@@ -342,8 +344,8 @@ hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                        int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
                        const int64_t *pitch_table, int groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one, map,
-                       rgb_table, pitch_table);
+    hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), kMaxSlots * one.d.hs * 4, s, b, one,
+                       rgb_one, pitch_one, map, rgb_table, pitch_table);
     return hipGetLastError();
 }
 
@@ -353,15 +355,15 @@ hipError_t launch_zero_mixed(const BatchArgs &b, const TickList &l, int groups, 
 }
 
 hipError_t launch_init_mixed(const BatchArgs &b, const TickList &l, int groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_mixed, dim3(groups), dim3(kThreads), 0, s, b, l);
+    hipLaunchKernelGGL(k_init_mixed, dim3(groups), dim3(kThreads), kMaxSlots * l.hs * 4, s, b, l);
     return hipGetLastError();
 }
 
 hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                          int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
                          const int64_t *pitch_table, int groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_rehist, dim3(groups), dim3(kThreads), 0, s, b, one, rgb_one, pitch_one,
-                       map, rgb_table, pitch_table);
+    hipLaunchKernelGGL(k_rehist, dim3(groups), dim3(kThreads), kRehistSlots * one.d.hs * 4, s, b,
+                       one, rgb_one, pitch_one, map, rgb_table, pitch_table);
     return hipGetLastError();
 }
 
