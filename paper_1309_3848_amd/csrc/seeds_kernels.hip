@@ -86,7 +86,6 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         if (local) {
             const int slot = (sy - sy_lo) * nsx + (sx - sx_lo);
             atomicAdd(&dyn_hist[slot * d.hs + j], 1);
-            atomicAdd(&sl.size[slot], 1);
         } else {
             atomicAdd(&st0[(int64_t)label * d.hs + j], 1);
             atomicAdd(&st0[khs + label], 1);
@@ -103,7 +102,11 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         const int label = (sy_lo + slot / nsx) * d.gx + sx_lo + slot % nsx;
         atomicAdd(&st0[(int64_t)label * d.hs + j], v);
         atomicAdd(&st1[(int64_t)label * d.hs + j], v);
+        // sizes from the non-zero cells (far fewer LDS atomics on one address
+        // than counting every pixel)
+        atomicAdd(&sl.size[slot], v);
     }
+    __syncthreads();
     for (int i = threadIdx.x; i < nslots; i += kThreads) {
         const int v = sl.size[i];
         if (!v) continue;
@@ -258,7 +261,6 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         const int s = e >= 0 ? r.slot[e] : -1;
         if (s >= 0) {
             atomicAdd(&dyn_hist[s * d.hs + j[q]], 1);
-            atomicAdd(&r.size[s], 1);
         } else {
             atomicAdd(&st0[(int64_t)k[q] * d.hs + j[q]], 1);
             atomicAdd(&st0[khs + k[q]], 1);
@@ -273,7 +275,9 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         const int s = i / d.hs, jj = i - s * d.hs;
         atomicAdd(&st0[(int64_t)r.label[s] * d.hs + jj], v);
         atomicAdd(&st1[(int64_t)r.label[s] * d.hs + jj], v);
+        atomicAdd(&r.size[s], v);  // sizes from the non-zero cells
     }
+    __syncthreads();
     for (int i = threadIdx.x; i < ns; i += kThreads) {
         const int v = r.size[i];
         if (!v) continue;
