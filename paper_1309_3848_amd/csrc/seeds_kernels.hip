@@ -227,6 +227,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         c2[q] = p[2];
         k[q] = lab[(int64_t)yc * d.W + xc];
     }
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < kRehistPx; ++q) {
         const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
@@ -234,9 +235,18 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         if (x < d.W && y < d.H) {
             j[q] = (((c0[q] * d.B) >> 8) * d.B + ((c1[q] * d.B) >> 8)) * d.B + ((c2[q] * d.B) >> 8);
             bins[(int64_t)y * d.W + x] = (uint8_t)j[q];
-            rehist_entry(r, k[q], true);
         } else {
             k[q] = -1;
+        }
+        // each distinct label of the wavefront is inserted once, by its first
+        // lane (neighbouring pixels mostly share labels: one insert per lane
+        // would queue on a single LDS address)
+        uint64_t pending = __ballot(k[q] >= 0);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int key = __shfl(k[q], leader);
+            if (lane == leader) rehist_entry(r, key, true);
+            pending &= ~__ballot(k[q] == key);
         }
     }
     __syncthreads();
