@@ -35,10 +35,7 @@ struct PhaseWork {
 // it runs after the replay prefetch is issued so that the two overlap.
 // KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
 // workgroup from its work).
-// PRE: log entries prefetched per workgroup (more for one image, where a long
-// log's extra round trip at the end holds up the launch; fewer for batches,
-// whose many workgroups would fetch mostly unused entries).
-template <bool BIG, int KINDS, bool COMPACT, int PRE, typename Find>
+template <bool BIG, int KINDS, bool COMPACT, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups,
                                            int slot_base = 0) {
@@ -53,8 +50,7 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     // blockIdx.x are fetched now, together with its length, and added at the
     // end; a longer log (rare) is read once its length is known.
     int32_t *W = pick(b.ar.state, par ^ 1);
-    constexpr int kPre = PRE;
-    static_assert(PRE <= kPT && (PRE & (PRE - 1)) == 0, "one entry per thread, power of two");
+    constexpr int kPre = 64;
     // (unconditional loads: the slot exists whatever replay_groups is)
     const bool replay_own = (int)blockIdx.x < replay_groups;
     const int64_t own_slot = (int64_t)(par ^ 1) * b.log_groups + blockIdx.x;
@@ -103,7 +99,7 @@ template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
     uint32_t stamp, int replay_groups, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, BATCH ? 64 : kPT>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
         b,
         [&]() {
             return PhaseWork{resolve<BATCH>(b, one, map, level, cls, remap), level, cls};
@@ -118,7 +114,7 @@ __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
 template <bool BIG, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, 64>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
         b,
         [&]() {
             const int lg = remap ? xcd_group() : (int)blockIdx.x;
