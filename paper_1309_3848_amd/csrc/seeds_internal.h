@@ -211,11 +211,11 @@ __host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
 }
 
 // Workgroups of one descend launch for an image and of one init launch.
-// A descend workgroup writes one row (a chunk of up to 256 units) of the
-// child grid.
+// A descend workgroup copies one row chunk of up to 256 units of `level` to
+// their children.
 __host__ __device__ inline int descend_groups(const Dims &d, int level) {
-    const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
-    return th * ((tw + kPersistentThreads - 1) / kPersistentThreads);
+    const int fw = units_w(d, level), fh = units_h(d, level);
+    return fh * ((fw + kPersistentThreads - 1) / kPersistentThreads);
 }
 constexpr int kInitTW = 64, kInitTH = 16;
 __host__ __device__ inline int init_groups(const Dims &d) {

@@ -580,16 +580,26 @@ __device__ inline void block_phase_any(const BatchArgs &b, const ImageView &v, i
 // (into the pixel labels from level 1).
 __device__ inline void descend(const ImageView &v, int level) {
     const Dims &d = v.d;
-    const int fw = units_w(d, level);
+    const int fw = units_w(d, level), fh = units_h(d, level);
     const int32_t *from = level_grid(v, level);
     int32_t *to = level == 1 ? v.lab : level_grid(v, level - 1);
     const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
-    // work item = (child row, chunk of kPT columns): no per-lane division
-    const int chunks = (tw + kPT - 1) / kPT;
-    const int items = th * chunks;
+    // work item = (parent row, chunk of kPT parents): each thread copies one
+    // parent label to its (up to) four children; no per-lane division
+    const int chunks = (fw + kPT - 1) / kPT;
+    const int items = fh * chunks;
     for (int it = v.grp; it < items; it += v.ngroups) {
-        const int y = it / chunks, x = (it - y * chunks) * kPT + (int)threadIdx.x;
-        if (x < tw) to[(int64_t)y * tw + x] = from[(int64_t)(y >> 1) * fw + (x >> 1)];
+        const int py = it / chunks, px = (it - py * chunks) * kPT + (int)threadIdx.x;
+        if (px >= fw) continue;
+        const int32_t l = from[(int64_t)py * fw + px];
+        const int x = 2 * px, y = 2 * py;  // x < tw and y < th: the child grid is 2f-1 or 2f wide
+        int32_t *row = to + (int64_t)y * tw + x;
+        row[0] = l;
+        if (x + 1 < tw) row[1] = l;
+        if (y + 1 < th) {
+            row[tw] = l;
+            if (x + 1 < tw) row[tw + 1] = l;
+        }
     }
 }
 
