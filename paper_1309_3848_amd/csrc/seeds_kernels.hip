@@ -39,6 +39,7 @@ __device__ __forceinline__ int grid_row(int y, const Dims &d, int bh) {
 extern __shared__ int32_t dyn_hist[];
 struct InitSlots {
     int32_t size[kMaxSlots];
+    int32_t col[kInitTW], row[kInitTH];  // superpixel column / row of the tile's columns / rows
 };
 
 // One tile of one image. st0 / st1: the image's state in both copies.
@@ -56,11 +57,6 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     const int nsx = sx_hi - sx_lo + 1;
     const int nslots = nsx * (sy_hi - sy_lo + 1);
     const bool local = nslots <= kMaxSlots;
-    if (local) {
-        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) dyn_hist[i] = 0;
-        for (int i = threadIdx.x; i < nslots; i += kThreads) sl.size[i] = 0;
-    }
-    __syncthreads();
     // every pixel's colour is loaded first, from addresses clamped into the
     // image (a load behind a branch is waited for at the end of the branch)
     constexpr int kRows = kInitTH * kInitTW / kThreads;
@@ -74,15 +70,29 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         c1[q] = p[1];
         c2[q] = p[2];
     }
+    if (local) {
+        for (int i = threadIdx.x; i < nslots * d.hs; i += kThreads) dyn_hist[i] = 0;
+        for (int i = threadIdx.x; i < nslots; i += kThreads) sl.size[i] = 0;
+    }
+    // the grid position of each column and row of the tile, one division
+    // each instead of two 64-bit divisions per pixel
+    if (threadIdx.x < kInitTW)
+        sl.col[threadIdx.x] = grid_col(min(x0 + (int)threadIdx.x, d.W - 1), d, bw);
+    else if (threadIdx.x < kInitTW + kInitTH)
+        sl.row[threadIdx.x - kInitTW] = grid_row(min(y0 + (int)threadIdx.x - kInitTW, d.H - 1), d, bh);
+    __syncthreads();
+    const int sh = __builtin_ctz(d.T);  // T is a power of two
+    const int sx = sl.col[threadIdx.x % kInitTW];
 #pragma unroll
     for (int q = 0; q < kRows; ++q) {
-        const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
+        const int r = (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
+        const int y = y0 + r;
         if (x >= d.W || y >= d.H) continue;
         const int j = (((c0[q] * d.B) >> 8) * d.B + ((c1[q] * d.B) >> 8)) * d.B + ((c2[q] * d.B) >> 8);
         bins[(int64_t)y * d.W + x] = (uint8_t)j;
-        const int sx = grid_col(x, d, bw), sy = grid_row(y, d, bh);
+        const int sy = sl.row[r];
         const int label = sy * d.gx + sx;
-        if (x % d.T == 0 && y % d.T == 0) top[(int64_t)(y / d.T) * bw + x / d.T] = label;
+        if (((x | y) & (d.T - 1)) == 0) top[(int64_t)(y >> sh) * bw + (x >> sh)] = label;
         if (local) {
             const int slot = (sy - sy_lo) * nsx + (sx - sx_lo);
             atomicAdd(&dyn_hist[slot * d.hs + j], 1);
