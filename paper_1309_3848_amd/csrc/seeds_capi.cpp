@@ -599,7 +599,7 @@ seeds_status labels_of(seeds_ctx *ctx, int32_t image, int32_t *out, int32_t out_
     }
     const int level = image_level(ctx, image);
     if (level == 0)
-        e = hipMemcpyAsync(dst, ctx->ar.lab + g.lab, bytes, hipMemcpyDeviceToDevice, s);
+        e = launch_copy(dst, ctx->ar.lab + g.lab, (int64_t)d.H * d.W, s);
     else
         e = launch_expand(d, image_units(ctx, image), level, dst, s);
     if (e == hipSuccess && out_is_host) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s);

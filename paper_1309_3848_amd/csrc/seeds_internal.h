@@ -235,6 +235,10 @@ struct PersistentGeom {
 // of the workgroup among that image's workgroups of the launch) and `groups`
 // is the launch's total.
 hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// n int32 from src to dst, both in device memory, by the copy-out kernel
+// spread over the whole device (a runtime copy when src is not 16-byte
+// aligned).
+hipError_t launch_copy(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
 hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                        int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
                        const int64_t *pitch_table, int groups, hipStream_t s);

@@ -336,9 +336,10 @@ __global__ __launch_bounds__(kThreads) void k_expand(const int32_t *__restrict__
     if (x < W) out[(int64_t)y * W + x] = blab[(int64_t)(y >> level) * uw + (x >> level)];
 }
 
-// Labels out to pinned host memory through a narrow kernel: a few workgroups
-// stream the copy over PCIe while the rest of the device keeps refining. The
-// source is 16-byte aligned; the destination takes 16-byte stores when it is.
+// Copy of labels. Out to pinned host memory it runs as a narrow kernel: a few
+// workgroups stream the copy over PCIe while the rest of the device keeps
+// refining; device to device it spreads over the whole device. The source is
+// 16-byte aligned; the destination takes 16-byte stores when it is.
 __global__ __launch_bounds__(kThreads) void k_copy_out(int32_t *__restrict__ dst,
                                                        const int32_t *__restrict__ src,
                                                        int64_t n) {
@@ -394,6 +395,17 @@ hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t
 hipError_t launch_copy_out(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s) {
     constexpr int kCopyGroups = 16;
     hipLaunchKernelGGL(k_copy_out, dim3(kCopyGroups), dim3(kThreads), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if ((uintptr_t)src & 15)
+        return hipMemcpyAsync(dst, src, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+    // the same copy over the whole device: one 16-byte piece per lane
+    const unsigned want = blocks_for((n + 3) / 4, kThreads);
+    const unsigned g = want > 8192u ? 8192u : want;
+    hipLaunchKernelGGL(k_copy_out, dim3(g), dim3(kThreads), 0, s, dst, src, n);
     return hipGetLastError();
 }
 
