@@ -280,6 +280,30 @@ def test_strided_rows(S):
     assert np.array_equal(lab.numpy(), ref)
 
 
+@pytest.mark.parametrize("H,W,K,L", [(37, 53, 12, 2), (321, 481, 200, 4)])
+def test_labels_into_outputs_at_every_alignment(S, H, W, K, L):
+    """Device label readback at offsets 0..4 ints into a larger buffer (only
+    offsets 0 and 4 allow 16-byte pieces; H W mod 4 = 1 leaves a ragged
+    tail): the labels equal the oracle's and nothing around them is written."""
+    import torch
+    from paper_1309_3848_amd import synth
+    _say(f"labels at every alignment {H}x{W}")
+    img = synth.voronoi_image(H, W, 9, 8.0, seed=71)
+    ref, _, _ = oracle.seeds(img, K, L, 5, 2, 1, 0)
+    n = H * W
+    ctx = S.seeds_init(torch.from_numpy(img).cuda(), K, S.make_params(L, 5, 2, 1, 0))
+    try:
+        S.seeds_refine(ctx)
+        for off in range(5):
+            buf = torch.full((n + 16,), -7, dtype=torch.int32, device="cuda")
+            S.seeds_labels(ctx, buf[off:off + n].view(H, W))
+            got = buf.cpu().numpy()
+            assert np.array_equal(got[off:off + n].reshape(H, W), ref), f"offset {off}"
+            assert (got[:off] == -7).all() and (got[off + n:] == -7).all(), f"offset {off}"
+    finally:
+        S.seeds_destroy(ctx)
+
+
 @pytest.mark.parametrize("rule", [0, 1])
 def test_graph_replays(S, rule):
     """The refinement graph is captured on the first refine and replayed by
