@@ -86,6 +86,8 @@ def schedule_bytes(h: int, w: int, levels: int, iters: int):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_phase_1080p_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_phase_batch64_traffic.json")
+STREAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_phase_stream4k_traffic.json")
 KERNEL_SOURCES = ["seeds_phase.h", "seeds_phase.hip", "seeds_device.h", "seeds_internal.h"]
 
 
@@ -98,11 +100,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per phase launch from the committed rocprofv3 FETCH_SIZE and
-    WRITE_SIZE runs, or None when the kernel sources changed since."""
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per phase launch of a workload from the committed rocprofv3
+    FETCH_SIZE and WRITE_SIZE runs, or None when the kernel sources changed
+    since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -249,7 +252,8 @@ def run_batch(args) -> int:
         "roofline": {"bound": "hbm", "kernel": "k_phase (batch variant; one phase of every "
                                                "image per launch)",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": measured_traffic(BATCH_TRAFFIC_FILE),
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "launches_per_batch": launches, "avg_launch_us": round(phase_us, 3),
                      "refine_ms": round(refine_ms, 4)},
@@ -390,7 +394,8 @@ def run_stream(args) -> int:
         "frame_generation_s": round(gen_s, 1),
         "roofline": {"bound": "hbm", "kernel": "k_phase (pixel-level phase of one 4K frame)",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": measured_traffic(STREAM_TRAFFIC_FILE),
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "launches_per_frame": launches, "avg_launch_us": round(phase_us, 3),
                      "refine_ms": round(refine_ms, 4)},
