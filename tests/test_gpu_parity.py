@@ -140,6 +140,19 @@ def test_edge_shapes(S, H, W, K, L, mode):
     _compare(S, img, K, L, B=5, I=3, gamma=1, mode=mode)
 
 
+@pytest.mark.parametrize("H,W,K,L", [
+    (48, 200, 2400, 1), (48, 200, 2400, 2), (96, 256, 1536, 1), (96, 256, 384, 3), (50, 201, 600, 2),
+])
+def test_tiles_meeting_many_superpixels(S, H, W, K, L, mode):
+    """Initial superpixels of 2x2 and 4x4 pixels: a 64 x 16 initialisation
+    tile meets 64-256 of them and counts straight into the global histograms;
+    8 x 8 superpixels (and a ragged 50 x 201 image) stay on the LDS path."""
+    from paper_1309_3848_amd import synth
+    assert oracle.grid(H, W, K, L) is not None
+    img = synth.voronoi_image(H, W, 12, 8.0, seed=H * 7 + W + L)
+    _compare(S, img, K, L, B=5, I=2, gamma=1, mode=mode)
+
+
 @pytest.mark.parametrize("compaction", [1, 0])
 @pytest.mark.parametrize("H,W", [
     (11, 189), (12, 190), (13, 191), (14, 192), (15, 193), (24, 194), (25, 195), (26, 196),

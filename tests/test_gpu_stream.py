@@ -58,7 +58,10 @@ def _check(got, o, what):
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
-@pytest.mark.parametrize("shape", [(96, 128, 20, 24, 3), (270, 480, 60, 300, 4)])
+# the last two: superpixels of 2x2 and 4x4 pixels, so a warm-start tile meets
+# more labels than its key table and slots hold (global-atomic path)
+@pytest.mark.parametrize("shape", [(96, 128, 20, 24, 3), (270, 480, 60, 300, 4),
+                                   (48, 200, 12, 2400, 1), (64, 192, 12, 768, 2)])
 def test_stream_matches_oracle_frame_by_frame(S, mode, shape):
     import torch
     H, W, R, K, L = shape
