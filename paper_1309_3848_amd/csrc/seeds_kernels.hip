@@ -224,7 +224,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
     // the thread's pixels: bins (written now) and labels, kept in registers.
     // Every pixel's loads go out first, from addresses clamped into the image
     // (a load behind a branch is waited for at the end of the branch).
-    int32_t k[kRehistPx], j[kRehistPx];
+    int32_t k[kRehistPx], j[kRehistPx], ent[kRehistPx];
     uint8_t c0[kRehistPx], c1[kRehistPx], c2[kRehistPx];
     const int x = x0 + (int)(threadIdx.x % kInitTW), xc = min(x, d.W - 1);
 #pragma unroll
@@ -250,13 +250,19 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         }
         // each distinct label of the wavefront is inserted once, by its first
         // lane (neighbouring pixels mostly share labels: one insert per lane
-        // would queue on a single LDS address)
+        // would queue on a single LDS address); every lane with that label
+        // keeps the entry, so the counting pass needs no second look-up
+        ent[q] = -1;
         uint64_t pending = __ballot(k[q] >= 0);
         while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int key = __shfl(k[q], leader);
-            if (lane == leader) rehist_entry(r, key, true);
-            pending &= ~__ballot(k[q] == key);
+            const int leader = __ffsll((unsigned long long)pending) - 1;  // wave-uniform
+            const int key = __builtin_amdgcn_readlane(k[q], leader);
+            int h = -1;
+            if (lane == leader) h = rehist_entry(r, key, true);
+            h = __builtin_amdgcn_readlane(h, leader);
+            const bool mine = k[q] == key;
+            if (mine) ent[q] = h;
+            pending &= ~__ballot(mine);
         }
     }
     __syncthreads();
@@ -277,8 +283,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
 #pragma unroll
     for (int q = 0; q < kRehistPx; ++q) {
         if (k[q] < 0) continue;
-        const int e = rehist_entry(r, k[q], false);
-        const int s = e >= 0 ? r.slot[e] : -1;
+        const int s = ent[q] >= 0 ? r.slot[ent[q]] : -1;
         if (s >= 0) {
             atomicAdd(&dyn_hist[s * d.hs + j[q]], 1);
         } else {
