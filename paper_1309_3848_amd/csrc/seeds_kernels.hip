@@ -238,6 +238,12 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         k[q] = lab[(int64_t)yc * d.W + xc];
     }
     const int lane = threadIdx.x & 63;
+    // the wavefront's last four (label, entry) pairs: the rows of one thread
+    // are 4 apart and mostly meet the same labels
+    constexpr int kSeen = 4;
+    int seen_key[kSeen], seen_ent[kSeen];
+#pragma unroll
+    for (int c = 0; c < kSeen; ++c) seen_key[c] = seen_ent[c] = -1;
 #pragma unroll
     for (int q = 0; q < kRehistPx; ++q) {
         const int y = y0 + (int)(threadIdx.x / kInitTW) + q * (kThreads / kInitTW);
@@ -257,9 +263,22 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         while (pending) {
             const int leader = __ffsll((unsigned long long)pending) - 1;  // wave-uniform
             const int key = __builtin_amdgcn_readlane(k[q], leader);
-            int h = -1;
-            if (lane == leader) h = rehist_entry(r, key, true);
-            h = __builtin_amdgcn_readlane(h, leader);
+            int h = -2;
+#pragma unroll
+            for (int c = 0; c < kSeen; ++c)
+                if (seen_key[c] == key) h = seen_ent[c];
+            if (h == -2) {
+                h = -1;
+                if (lane == leader) h = rehist_entry(r, key, true);
+                h = __builtin_amdgcn_readlane(h, leader);
+#pragma unroll
+                for (int c = kSeen - 1; c > 0; --c) {
+                    seen_key[c] = seen_key[c - 1];
+                    seen_ent[c] = seen_ent[c - 1];
+                }
+                seen_key[0] = key;
+                seen_ent[0] = h;
+            }
             const bool mine = k[q] == key;
             if (mine) ent[q] = h;
             pending &= ~__ballot(mine);
