@@ -5,7 +5,9 @@ TEST INFRASTRUCTURE: only ``tests/``, ``__graft_entry__.smoke()`` and the
 (``paper_1309_3848_amd``) never does.
 
 The oracle is single-threaded C built with gcc; ``build()`` compiles it into
-``oracle/libseeds_oracle.so``.
+``oracle/libseeds_oracle.so``, and the same source with ``-fopenmp`` into
+``oracle/libseeds_oracle_omp.so`` (the all-core CPU baseline: the units of a
+phase are decided in parallel; results are identical to the serial build).
 """
 from __future__ import annotations
 
@@ -18,18 +20,21 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "seeds_oracle.c")
 LIB = os.path.join(HERE, "libseeds_oracle.so")
+LIB_OMP = os.path.join(HERE, "libseeds_oracle_omp.so")
 
 RULE_INTERSECT = 0
 RULE_EXACT = 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no vector intrinsics)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-Wall", "-Wextra",
-                        "-o", tmp, SRC], check=True)
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2, no vector intrinsics), serial and
+    all-core (-fopenmp) builds."""
+    for lib_path, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(SRC):
+            tmp = lib_path + ".tmp"
+            subprocess.run(["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-Wall", "-Wextra",
+                            "-Wno-unknown-pragmas", *extra, "-o", tmp, SRC], check=True)
+            os.replace(tmp, lib_path)
     return LIB
 
 
@@ -83,6 +88,8 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_seeds.restype = I32
     L.oracle_quality.argtypes = [P, P, I32, I32, I32, I32, I32, P]
     L.oracle_quality.restype = I32
+    L.oracle_threads.argtypes = []
+    L.oracle_threads.restype = I32
     return L
 
 
@@ -99,6 +106,20 @@ def lib() -> ctypes.CDLL:
             build(force=True)
         _lib = load(LIB)
     return _lib
+
+
+_lib_omp = None
+
+
+def lib_omp() -> ctypes.CDLL:
+    """The all-core build (OpenMP over the units of a phase; threads from
+    OMP_NUM_THREADS)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(LIB_OMP) or os.path.getmtime(LIB_OMP) < os.path.getmtime(SRC):
+            build(force=True)
+        _lib_omp = load(LIB_OMP)
+    return _lib_omp
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -440,6 +440,30 @@ static void decide_unit(const oracle_state *st, int ux, int uy, oracle_decision 
  * updating anything. Returns the number of class units written to out
  * (at most max_out; pass out = NULL to count only).                    */
 int oracle_decide_class(const oracle_state *st, int cls, oracle_decision *out, int max_out) {
+#ifdef _OPENMP
+    /* All-core build (gcc -fopenmp): the decisions of a phase read only the
+     * phase-start state, so the rows of the class lattice are decided in
+     * parallel; each decision goes to its raster position among the class
+     * units, which gives the same array as the loop below.              */
+    const int rows = st->uh > cls / 3 ? (st->uh - cls / 3 + 2) / 3 : 0;
+    const int cols = st->uw > cls % 3 ? (st->uw - cls % 3 + 2) / 3 : 0;
+#pragma omp parallel
+    {
+        int64_t *thl = (int64_t *)malloc(sizeof(int64_t) * st->nbins);
+        int64_t *thkl = (int64_t *)malloc(sizeof(int64_t) * st->nbins);
+#pragma omp for schedule(dynamic, 4)
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) {
+                oracle_decision d;
+                decide_unit(st, cls % 3 + 3 * c, cls / 3 + 3 * r, &d, thl, thkl);
+                const int at = r * cols + c;
+                if (out && at < max_out) out[at] = d;
+            }
+        free(thl);
+        free(thkl);
+    }
+    return rows * cols;
+#endif
     int64_t *hl = (int64_t *)malloc(sizeof(int64_t) * st->nbins);
     int64_t *hkl = (int64_t *)malloc(sizeof(int64_t) * st->nbins);
     int cnt = 0;
@@ -562,6 +586,15 @@ void oracle_run_sequential(oracle_state *st) {
 
 /* ------------------------------------------------------------------ */
 /* Accessors */
+/* Threads a phase's decisions use: omp_get_max_threads() in the all-core
+ * build, 1 otherwise.                                                   */
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }
+#else
+int oracle_threads(void) { return 1; }
+#endif
+
 int oracle_num_superpixels(const oracle_state *st) { return st->K; }
 int oracle_level(const oracle_state *st) { return st->level; }
 void oracle_unit_grid(const oracle_state *st, int *uw, int *uh) { *uw = st->uw; *uh = st->uh; }

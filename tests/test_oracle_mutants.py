@@ -44,6 +44,11 @@ MUTANTS = [
     ("apply-size-not-moved", "st->size[n] += 1;", "st->size[n] += 0;", 0),
     ("drop-rule-wrong-side", "is_source[dec[i].n]", "is_source[dec[i].k]", 0),
     ("energy-G-not-squared", "gs += (int64_t)cnts[i] * cnts[i];", "gs += (int64_t)cnts[i];", 0),
+    ("sequential-column-order",
+     "for (int uy = 0; uy < st->uh; ++uy)\n                for (int ux = 0; ux < st->uw; ++ux) {",
+     "for (int ux = 0; ux < st->uw; ++ux)\n                for (int uy = 0; uy < st->uh; ++uy) {", 0),
+    ("sequential-skips-half-the-moves", "if (d.accepted) apply_move(st, ux, uy, d.k, d.n);",
+     "if (d.accepted && ((ux + uy) & 1)) apply_move(st, ux, uy, d.k, d.n);", 0),
 ]
 
 

@@ -604,6 +604,110 @@ def test_sequential_variant_reaches_similar_energy():
     assert E[16][0] >= E[4][1]
 
 
+def _ring_keeps_k(ulab, x, y, k):
+    """Local 4-connectivity test of the readings (from the definition): take
+    the 3x3 window of unit (x, y) (cells outside the grid are not k), remove
+    the unit itself, and require that every edge neighbour of label k is
+    reached from one of them by 4-steps over k-cells inside the window."""
+    h, w = ulab.shape
+    isk = {(dy, dx): 0 <= y + dy < h and 0 <= x + dx < w and ulab[y + dy, x + dx] == k
+           for dy in (-1, 0, 1) for dx in (-1, 0, 1)}
+    isk[(0, 0)] = False
+    edges = [c for c in ((-1, 0), (0, 1), (1, 0), (0, -1)) if isk[c]]
+    if not edges:
+        return False
+    seen, todo = {edges[0]}, [edges[0]]
+    while todo:
+        cy, cx = todo.pop()
+        for ny, nx in ((cy - 1, cx), (cy + 1, cx), (cy, cx - 1), (cy, cx + 1)):
+            if (ny, nx) in isk and isk[(ny, nx)] and (ny, nx) not in seen:
+                seen.add((ny, nx))
+                todo.append((ny, nx))
+    return all(c in seen for c in edges)
+
+
+def _sequential_reference(ulab, level, levels, bins, K, nb, iters, gamma, rule):
+    """The sequential variant by brute force: levels from `level` down to 0,
+    iters raster sweeps each; every unit in turn takes its best 4-neighbour
+    label (ties: the smaller) if that raises the energy, with the energy
+    recomputed from scratch for every candidate, and the move is applied at
+    once. Block levels judge by H' (exact rule) or by Prop. 1 in rationals."""
+    H, W = bins.shape
+    for lev in range(level, -1, -1):
+        if lev < level:
+            ulab = np.repeat(np.repeat(ulab, 2, 0), 2, 1)[:-(-H // (1 << lev)), :-(-W // (1 << lev))]
+        s = 1 << lev
+        uh, uw = ulab.shape
+        for _ in range(iters):
+            for y in range(uh):
+                for x in range(uw):
+                    k = int(ulab[y, x])
+                    cand = _candidates(ulab, x, y)
+                    if not cand or not _ring_keeps_k(ulab, x, y, k):
+                        continue
+                    plab = upsample(ulab, s, H, W)
+                    best, bn = None, None
+                    if lev == 0 or rule == oracle.RULE_EXACT:
+                        g_on = gamma if lev == 0 else 0
+                        E0 = energy(plab, bins, K, nb, g_on)
+                        for n in cand:
+                            t = ulab.copy()
+                            t[y, x] = n
+                            g = energy(upsample(t, s, H, W), bins, K, nb, g_on) - E0
+                            if best is None or g > best:
+                                best, bn = g, n
+                        take = best > 0
+                    else:
+                        hist = colour_histograms(plab, bins, K, nb)
+                        size = hist.sum(1)
+                        blk = bins[y * s:(y + 1) * s, x * s:(x + 1) * s]
+                        hl = np.bincount(blk.ravel(), minlength=nb)
+                        m = blk.size
+                        for n in cand:
+                            v = intersection(hist[n], int(size[n]), hl, m)
+                            if best is None or v > best:
+                                best, bn = v, n
+                        take = best > intersection(hist[k] - hl, int(size[k]) - m, hl, m)
+                    if take:
+                        ulab[y, x] = bn
+    return ulab
+
+
+@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("rule", [oracle.RULE_INTERSECT, oracle.RULE_EXACT])
+def test_sequential_variant_brute_force(seed, rule):
+    """oracle_run_sequential against a raster loop written from the
+    definitions on tiny images. Each draw is kept only if the reference moves
+    something (a draw where nothing moves pins nothing); redraws are seeded."""
+    rng = np.random.default_rng(5000 + 97 * seed + rule)
+    while True:
+        H, W = int(rng.integers(6, 11)), int(rng.integers(6, 11))
+        L = int(rng.integers(1, 3))
+        B = int(rng.integers(1, 3))
+        gamma = int(rng.choice([0, 1, 2]))
+        iters = int(rng.integers(1, 3))
+        # a few flat regions plus noise, so that moves pay off
+        base = rng.integers(0, 256, (3, 3))
+        rgb = np.repeat(np.repeat(base, -(-H // 3), 0), -(-W // 3), 1)[:H, :W]
+        rgb = np.clip(rgb[:, :, None] + rng.integers(-40, 41, (H, W, 3)), 0, 255).astype(np.uint8)
+        K = int(rng.integers(2, 6))
+        try:
+            o = oracle.Oracle(rgb, K=K, levels=L, bins=B, iters=iters, gamma=gamma, rule=rule)
+        except ValueError:
+            continue
+        start = o.unit_labels().copy()
+        want = _sequential_reference(start.copy(), L - 1, L, o.bins(), o.K, o.nbins, iters,
+                                     gamma, rule)
+        if np.array_equal(upsample(want, 1, H, W), upsample(start, 1 << (L - 1), H, W)):
+            continue
+        o.run_sequential()
+        assert np.array_equal(o.labels(), want), (H, W, L, B, gamma, iters, K)
+        assert o.invalid_superpixels() == 0
+        hist, size = o.histograms()
+        assert np.array_equal(hist, colour_histograms(want, o.bins(), o.K, o.nbins))
+        return
+
+
 def test_exact_zero_gain_is_rejected():
     """Flat image, 2x2 blocks, ragged last row (3 rows): block (2,0) of label 0
     (m = 4 pixels) next to label 1. Sizes |A_0| = 14, |A_1| = 10, so the exact
