@@ -146,9 +146,43 @@ int32_t seeds_level(const seeds_ctx *ctx);
  *               border), on the pixel labels seeds_labels would return.
  * Hill climbing with the exact block rule never lowers H' at block levels,
  * nor H' + gamma G' at pixel level. SEEDS_E_INVAL for NULL outputs; the call
- * allocates a little device memory in stream order and waits for the stream. */
+ * waits for the stream (no allocation: it uses the context's own memory).   */
 seeds_status seeds_energy(const seeds_ctx *ctx, int64_t *h_energy, int64_t *g_energy,
                           void *hip_stream);
+
+/* Test hook: the boundary units of every image of the context (Sec. 5.2: a
+ * block, or at pixel level a pixel, whose 4-neighbourhood in the image holds
+ * another label; only these units are proposed for a move, and only their
+ * colour bins are read to decide). Counted on the unit grid of `level`:
+ * level = -1 is each image's current level; level in [0, seeds_level(ctx)]
+ * is min(level, L - 1) of each image, with the labels its units inherit from
+ * the current grid (as after the level transitions that precede the next
+ * phase at that level). For class cls in [0,8] (units with
+ * 3 (uy mod 3) + (ux mod 3) = cls) or every class (cls = -1), units[i] and
+ * pixels[i] (host arrays of seeds_batch_count entries; either may be NULL)
+ * receive image i's boundary units and the image pixels they cover. Waits
+ * for the stream; no allocation.                                            */
+seeds_status seeds_boundary_units(const seeds_ctx *ctx, int32_t level, int32_t cls,
+                                  int64_t *units, int64_t *pixels, void *hip_stream);
+
+/* ---- Snapshots -----------------------------------------------------------
+ * The refinement can be stopped after any phase and resumed later (Sec. 5.4:
+ * the partition is valid at every step). A snapshot holds the whole state of
+ * a context between calls: every image's colour bins, its labels on the unit
+ * grid of its current level, its colour histograms and sizes, and the
+ * schedule cursor (level, sweep, class). Restored into a context created for
+ * images of the same sizes, K, levels and parameters (seeds_init or
+ * seeds_batch_init, any pixels), the context continues exactly as the
+ * original would have: labels, histograms and sizes bit for bit.
+ * seeds_snapshot_size gives the bytes the current state needs (it depends on
+ * the level). seeds_snapshot writes them to host memory `host` of `bytes`
+ * bytes (SEEDS_E_INVAL if too small) and waits for the stream; seeds_restore
+ * reads them back (SEEDS_E_INVAL, before any device work, for a buffer that
+ * is not a snapshot of a matching context) and waits for the stream. A
+ * snapshot is native-endian and tied to this library version.             */
+seeds_status seeds_snapshot_size(const seeds_ctx *ctx, int64_t *bytes);
+seeds_status seeds_snapshot(const seeds_ctx *ctx, void *host, int64_t bytes, void *hip_stream);
+seeds_status seeds_restore(seeds_ctx *ctx, const void *host, int64_t bytes, void *hip_stream);
 
 typedef enum {
     SEEDS_LAUNCH_GRAPH = 0,      /* default: one kernel per phase, the launches of a
@@ -380,6 +414,15 @@ typedef struct {
 seeds_status seeds_quality_metrics(const int32_t *labels, const int32_t *truth, int32_t H,
                                    int32_t W, int32_t num_labels, int32_t num_truth, int32_t eps,
                                    seeds_quality *out, void *hip_stream);
+
+/* ---- Measurement ----------------------------------------------------------
+ * LDS-atomic throughput of the current device, the secondary roof of the
+ * refinement kernels: 4096 workgroups of 256 lanes each add 1024 times to
+ * their own LDS word (no bank or address conflicts), timed with events on
+ * hip_stream (best of three after a warm-up). *ginst_per_s receives 64-lane
+ * wavefront atomic instructions per second, in units of 1e9. Allocates a
+ * little device memory and waits for the stream.                          */
+seeds_status seeds_lds_atomic_rate(double *ginst_per_s, void *hip_stream);
 
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */

@@ -60,13 +60,6 @@ struct CachedGraph {
 
 constexpr int kGraphSlots = 4;
 
-// Workgroups of one launch: the map (device array of (image, rank) per
-// logical workgroup; nullptr for a single image) and their number.
-struct LaunchMap {
-    const int2 *map = nullptr;
-    int groups = 0;
-};
-
 }  // namespace
 
 struct seeds_ctx {
@@ -79,6 +72,8 @@ struct seeds_ctx {
     int64_t state_elems = 0;      // elements of one state copy (all images)
     int64_t src_elems = 0;
     ImageDesc *d_imgs = nullptr;  // device copy of imgs
+    unsigned long long *hook = nullptr;  // test-hook counters: 2 per image
+    int32_t *stage = nullptr;  // int32 pixel labels of one image (readback, hooks)
     const uint8_t **d_rgb = nullptr;  // batch: device table of image pointers
     int64_t *d_pitch = nullptr;       // batch: device table of row pitches
     std::vector<const uint8_t *> rgb;  // host copies of the two tables
@@ -108,6 +103,10 @@ seeds_status device_error(seeds_ctx *ctx, hipError_t e, const char *what) {
     if (ctx) ctx->poisoned = true;
     return fail(SEEDS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace
+
+namespace seeds {
 
 // Superpixel grid (Sec. 5.1): gx = round(sqrt(K W / H)) with halves rounding
 // up, i.e. the largest g >= 1 with (2g - 1)^2 H <= 4 K W; gy = round(K / gx).
@@ -163,6 +162,10 @@ seeds_status check_params(int32_t H, int32_t W, int32_t K, const seeds_params *p
     return SEEDS_OK;
 }
 
+}  // namespace seeds
+
+namespace {
+
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 size_t round64(size_t v) { return (v + 63) & ~(size_t)63; }
 
@@ -193,10 +196,10 @@ LaunchMap init_launch(const seeds_ctx *ctx) {
 int image_level(const seeds_ctx *ctx, int i) {
     return std::min(ctx->sched.level, ctx->imgs[i].d.L - 1);
 }
-const int32_t *image_units(const seeds_ctx *ctx, int i) {
+// The int32 block grid holding image i's labels (level >= 1).
+const int32_t *image_grid(const seeds_ctx *ctx, int i) {
     const ImageDesc &g = ctx->imgs[i];
-    const int l = image_level(ctx, i);
-    return l == 0 ? ctx->ar.lab + g.lab : ctx->ar.bl + g.bl[l & 1];
+    return ctx->ar.bl + g.bl[image_level(ctx, i) & 1];
 }
 
 seeds_status start_schedule(seeds_ctx *ctx, hipStream_t s) {
@@ -216,30 +219,37 @@ seeds_status start_schedule(seeds_ctx *ctx, hipStream_t s) {
     return SEEDS_OK;
 }
 
-// Enqueue the schedule from the current cursor as per-phase launches (at
-// most max_phases phases; < 0: all), ending with the replay that makes both
-// state copies equal again.
-seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out, hipStream_t s) {
-    const Dims &top = ctx->top;
+}  // namespace
+
+namespace seeds {
+
+// Enqueue the schedule from the cursor as per-phase launches (at most
+// max_phases phases; < 0: all), ending with the replay that makes both state
+// copies equal again.
+hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_phases,
+                            int32_t *done_out, hipStream_t s) {
+    const Dims &top = a.top;
     const bool exact = top.rule == SEEDS_BLOCK_EXACT;
-    const BatchArgs b = batch_args(ctx);
-    const ImageDesc &one = ctx->imgs[0];
+    const BatchArgs &b = a.b;
+    const ImageDesc &one = a.one;
     int32_t done = 0;
     int par = 0, prev_groups = 0;
     uint32_t stamp = 0;
     hipError_t e = hipSuccess;
-    if (exact) e = launch_fill(ctx->ar.src, 0, ctx->src_elems, s);
+    if (exact) e = launch_fill(b.ar.src, 0, a.src_elems, s);
     for (;;) {
-        if (e != hipSuccess) return device_error(ctx, e, "phase launch");
+        if (e != hipSuccess) return e;
         int cls = 0;
-        const SchedOp op = sched_next(top, ctx->sched, max_phases < 0 ? -1 : max_phases - done, &cls);
+        const SchedOp op = sched_next(top, sched, max_phases < 0 ? -1 : max_phases - done, &cls);
         if (op == OP_END) break;
         if (op == OP_DESCEND) {
-            const LaunchMap m = descend_launch(ctx, ctx->sched.level);
-            if (m.groups > 0) e = launch_descend(b, one, m.map, ctx->sched.level, m.groups, s);
+            const LaunchMap m = a.phase_map ? a.descend_map[sched.level]
+                                            : LaunchMap{nullptr, descend_groups(one.d, sched.level)};
+            if (m.groups > 0) e = launch_descend(b, one, m.map, sched.level, m.groups, s);
         } else {
-            const int level = ctx->sched.level;
-            const LaunchMap m = phase_launch(ctx, level, cls);
+            const int level = sched.level;
+            const LaunchMap m = a.phase_map ? a.phase_map[level * 9 + cls]
+                                            : LaunchMap{nullptr, phase_groups(one.d, level, cls)};
             ++stamp;
             if (m.groups == 0) {
                 // no unit of this class in any image: nothing moves; the
@@ -251,24 +261,41 @@ seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_ou
             } else {
                 if (level > 0 && exact) {
                     e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 1, stamp, m.groups,
-                                     prev_groups, ctx->tune, s);
+                                     prev_groups, a.tune, s);
                     if (e == hipSuccess)
                         e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 2, stamp,
-                                         m.groups, 0, ctx->tune, s);
+                                         m.groups, 0, a.tune, s);
                 } else {
                     e = launch_phase(b, one, m.map, top.L - 1, level, cls, par, 0, stamp, m.groups,
-                                     prev_groups, ctx->tune, s);
+                                     prev_groups, a.tune, s);
                 }
                 prev_groups = m.groups;
                 par ^= 1;
             }
             ++done;
         }
-        sched_done(ctx->sched, op);
+        sched_done(sched, op);
     }
     if (e == hipSuccess && prev_groups > 0) e = launch_final_replay(b, par ^ 1, prev_groups, s);
-    if (e != hipSuccess) return device_error(ctx, e, "replay launch");
-    if (done_out) *done_out = done;
+    if (e == hipSuccess && done_out) *done_out = done;
+    return e;
+}
+
+}  // namespace seeds
+
+namespace {
+
+seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out, hipStream_t s) {
+    ScheduleArgs a;
+    a.b = batch_args(ctx);
+    a.one = ctx->imgs[0];
+    a.top = ctx->top;
+    a.phase_map = ctx->nimg > 1 ? ctx->phase_map.data() : nullptr;
+    a.descend_map = ctx->nimg > 1 ? ctx->descend_map.data() : nullptr;
+    a.src_elems = ctx->src_elems;
+    a.tune = ctx->tune;
+    const hipError_t e = enqueue_schedule(a, ctx->sched, max_phases, done_out, s);
+    if (e != hipSuccess) return device_error(ctx, e, "phase launch");
     return SEEDS_OK;
 }
 
@@ -421,7 +448,13 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
         return fail(SEEDS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     }
     ctx->top = in[0].d;
-    for (const auto &im : in) ctx->top.L = std::max(ctx->top.L, im.d.L);
+    bool lab16 = true;
+    size_t max_n = 0;
+    for (const auto &im : in) {
+        ctx->top.L = std::max(ctx->top.L, im.d.L);
+        lab16 &= im.d.K <= kLab16MaxK;
+        max_n = std::max(max_n, (size_t)im.d.H * im.d.W);
+    }
     const int Lmax = ctx->top.L;
     // offsets of every image in the arenas; image 0 starts every arena at
     // offset 0, which the single-image kernels rely on
@@ -495,10 +528,12 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
         off += align_up(bytes);
         return o;
     };
-    const size_t o_bins = take(bins), o_lab = take(lab * 4), o_bl = take(bl * 4);
+    const size_t o_bins = take(bins), o_lab = take(lab * (lab16 ? 2 : 4)), o_bl = take(bl * 4);
     const size_t o_state = take(2 * state * 4), o_src = take(src * 4), o_pend = take(pend * 4);
     const size_t o_log = take(2 * log_entries * 8), o_logn = take(2 * log_slots * 4);
     const size_t o_sync = take(16);
+    const size_t o_hook = take(16 * std::max<size_t>(2, ctx->imgs.size()));
+    const size_t o_stage = take(max_n * 4);
     const size_t o_imgs = take(ctx->imgs.size() * sizeof(ImageDesc));
     const size_t o_rgb = take(ctx->imgs.size() * sizeof(void *));
     const size_t o_pitch = take(ctx->imgs.size() * sizeof(int64_t));
@@ -519,7 +554,8 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     }
     char *base = (char *)ctx->slab;
     ctx->ar.bins = (uint8_t *)(base + o_bins);
-    ctx->ar.lab = (int32_t *)(base + o_lab);
+    ctx->ar.lab = lab16 ? nullptr : (int32_t *)(base + o_lab);
+    ctx->ar.lab16 = lab16 ? (uint16_t *)(base + o_lab) : nullptr;
     ctx->ar.bl = (int32_t *)(base + o_bl);
     ctx->ar.state[0] = (int32_t *)(base + o_state);
     ctx->ar.state[1] = ctx->ar.state[0] + state;
@@ -528,6 +564,8 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     ctx->ar.log = (int2 *)(base + o_log);
     ctx->ar.log_n = (int32_t *)(base + o_logn);
     ctx->ar.sync = (uint32_t *)(base + o_sync);
+    ctx->hook = (unsigned long long *)(base + o_hook);
+    ctx->stage = (int32_t *)(base + o_stage);
     ctx->d_imgs = (ImageDesc *)(base + o_imgs);
     ctx->d_rgb = (const uint8_t **)(base + o_rgb);
     ctx->d_pitch = (int64_t *)(base + o_pitch);
@@ -584,33 +622,51 @@ seeds_status check_image(const seeds_ctx *ctx, int32_t image) {
     return check_usable(ctx);
 }
 
+// Image i's pixel labels as int32 in device memory: the int32 pixel plane
+// itself, or the staging buffer holding the 16-bit plane widened or a block
+// grid expanded (stream-ordered: valid until the next use of the buffer).
+const int32_t *pixel_labels32(seeds_ctx *ctx, int32_t image, hipError_t *e, hipStream_t s) {
+    const ImageDesc &g = ctx->imgs[image];
+    const int level = image_level(ctx, image);
+    if (level > 0) {
+        *e = launch_expand(g.d, image_grid(ctx, image), level, ctx->stage, s);
+        return ctx->stage;
+    }
+    if (ctx->ar.lab) {
+        *e = hipSuccess;
+        return ctx->ar.lab + g.lab;
+    }
+    *e = launch_copy_labels(ctx->stage, ctx->ar, g.lab, (int64_t)g.d.H * g.d.W, s);
+    return ctx->stage;
+}
+
+// Image i's labels on the unit grid of its current level, as int32.
+const int32_t *units32(seeds_ctx *ctx, int32_t image, hipError_t *e, hipStream_t s) {
+    if (image_level(ctx, image) > 0) {
+        *e = hipSuccess;
+        return image_grid(ctx, image);
+    }
+    return pixel_labels32(ctx, image, e, s);
+}
+
 seeds_status labels_of(seeds_ctx *ctx, int32_t image, int32_t *out, int32_t out_is_host,
                        hipStream_t s) {
     const ImageDesc &g = ctx->imgs[image];
     const Dims &d = g.d;
-    const size_t bytes = (size_t)d.H * d.W * 4;
-    int32_t *dst = out;
-    void *stage = nullptr;
-    hipError_t e;
-    if (out_is_host) {
-        e = hipMallocAsync(&stage, bytes, s);
-        if (e != hipSuccess) return device_error(nullptr, e, "hipMallocAsync");
-        dst = (int32_t *)stage;
-    }
     const int level = image_level(ctx, image);
-    if (level == 0)
-        e = launch_copy(dst, ctx->ar.lab + g.lab, (int64_t)d.H * d.W, s);
-    else
-        e = launch_expand(d, image_units(ctx, image), level, dst, s);
-    if (e == hipSuccess && out_is_host) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s);
-    if (out_is_host) {
-        hipError_t e2 = hipFreeAsync(stage, s);
-        if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipError_t e;
+    if (!out_is_host) {
+        e = level == 0 ? launch_copy_labels(out, ctx->ar, g.lab, (int64_t)d.H * d.W, s)
+                       : launch_expand(d, image_grid(ctx, image), level, out, s);
+        if (e != hipSuccess) return device_error(ctx, e, "labels copy");
+        return SEEDS_OK;
     }
+    const int32_t *lab = pixel_labels32(ctx, image, &e, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, lab, (size_t)d.H * d.W * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_error(ctx, e, "labels copy");
-    if (out_is_host) return check_device_flag(ctx, s);
-    return SEEDS_OK;
+    return check_device_flag(ctx, s);
 }
 
 seeds_status histograms_of(seeds_ctx *ctx, int32_t image, int32_t *hist, int32_t *size,
@@ -637,28 +693,42 @@ seeds_status histograms_of(seeds_ctx *ctx, int32_t image, int32_t *hist, int32_t
 seeds_status energy_of(seeds_ctx *ctx, int32_t image, int64_t *h_energy, int64_t *g_energy,
                        hipStream_t s) {
     const ImageDesc &g = ctx->imgs[image];
-    const Dims &d = g.d;
-    const int level = image_level(ctx, image);
-    const size_t lab_bytes = level == 0 ? 0 : (size_t)d.H * d.W * 4;
-    void *buf = nullptr;
-    hipError_t e = hipMallocAsync(&buf, 16 + lab_bytes, s);
-    if (e != hipSuccess) return device_error(nullptr, e, "hipMallocAsync");
-    unsigned long long *cnt = (unsigned long long *)buf;
-    const int32_t *lab = ctx->ar.lab + g.lab;
-    if (level > 0) {
-        int32_t *pix = (int32_t *)((char *)buf + 16);
-        e = launch_expand(d, image_units(ctx, image), level, pix, s);
-        lab = pix;
-    }
+    hipError_t e;
+    const int32_t *lab = pixel_labels32(ctx, image, &e, s);
     unsigned long long host[2] = {0, 0};
-    if (e == hipSuccess) e = launch_energy(ctx->ar.state[0] + g.state, d, lab, cnt, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, cnt, 16, hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipFreeAsync(buf, s);
-    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = launch_energy(ctx->ar.state[0] + g.state, g.d, lab, ctx->hook, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, ctx->hook, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_error(ctx, e, "energy");
     *h_energy = (int64_t)host[0];
     *g_energy = (int64_t)host[1];
+    return check_device_flag(ctx, s);
+}
+
+// Boundary units of class cls (< 0: all) of every image on the unit grid of
+// `level` (< 0: the image's current level; otherwise min(level, L - 1) of the
+// image, which the caller keeps at or below its current level), and the
+// pixels they cover; host outputs, waits for the stream.
+seeds_status boundary_of(seeds_ctx *ctx, int32_t level, int32_t cls, int64_t *units,
+                         int64_t *pixels, hipStream_t s) {
+    const int n = ctx->nimg;
+    hipError_t e = launch_fill((int32_t *)ctx->hook, 0, 4 * (int64_t)n, s);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const int cur = image_level(ctx, i);
+        const int l = level < 0 ? cur : std::min(level, ctx->imgs[i].d.L - 1);
+        const int32_t *units = units32(ctx, i, &e, s);
+        if (e == hipSuccess)
+            e = launch_boundary(units, ctx->imgs[i].d, cur, l, cls, ctx->hook + 2 * i, s);
+    }
+    std::vector<unsigned long long> host(2 * (size_t)n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host.data(), ctx->hook, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(ctx, e, "boundary count");
+    for (int i = 0; i < n; ++i) {
+        if (units) units[i] = (int64_t)host[2 * i];
+        if (pixels) pixels[i] = (int64_t)host[2 * i + 1];
+    }
     return check_device_flag(ctx, s);
 }
 
@@ -720,6 +790,189 @@ seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t
     ctx->sched.cur_sweep = 0;
     ctx->sched.cur_class = 0;
     ctx->cold = false;
+    ctx->last_stream = s;
+    return SEEDS_OK;
+}
+
+// ---- Snapshots -----------------------------------------------------------
+// Layout of a snapshot (host memory, native byte order): a SnapHeader, one
+// SnapImage per image, then per image its bins (H W bytes), its labels on the
+// unit grid of its current level (4 B per unit) and its colour histograms and
+// sizes (K hs + K int32, the context's row stride), each part starting at a
+// multiple of 8 bytes.
+constexpr uint64_t kSnapMagic = 0x31504e5344454553ull;  // "SEEDSNP1"
+
+struct SnapHeader {
+    uint64_t magic;
+    int32_t nimg;
+    int32_t B, I, gamma, rule;
+    int32_t level, cur_level, cur_sweep, cur_class, cold;
+    int64_t bytes;
+};
+
+struct SnapImage {
+    int32_t H, W, K, L;
+};
+
+size_t up8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+int64_t unit_count(const Dims &d, int level) { return (int64_t)units_w(d, level) * units_h(d, level); }
+
+// Bytes of a snapshot of ctx with its cursor at `level` (the images' unit
+// grids depend on it).
+int64_t snapshot_bytes(const seeds_ctx *ctx, int level) {
+    size_t b = up8(sizeof(SnapHeader)) + up8(sizeof(SnapImage) * ctx->nimg);
+    for (const auto &g : ctx->imgs) {
+        const Dims &d = g.d;
+        const int l = std::min(level, d.L - 1);
+        b += up8((size_t)d.H * d.W) + up8((size_t)unit_count(d, l) * 4) +
+             up8(((size_t)d.K * d.hs + d.K) * 4);
+    }
+    return (int64_t)b;
+}
+
+seeds_status snapshot(seeds_ctx *ctx, void *host, int64_t bytes, hipStream_t s) {
+    const int64_t need = snapshot_bytes(ctx, ctx->sched.level);
+    if (bytes < need)
+        return fail(SEEDS_E_INVAL, "snapshot buffer of %lld bytes < %lld", (long long)bytes,
+                    (long long)need);
+    char *p = (char *)host;
+    SnapHeader h{};
+    h.magic = kSnapMagic;
+    h.nimg = ctx->nimg;
+    h.B = ctx->top.B;
+    h.I = ctx->top.I;
+    h.gamma = ctx->top.gamma;
+    h.rule = ctx->top.rule;
+    h.level = ctx->sched.level;
+    h.cur_level = ctx->sched.cur_level;
+    h.cur_sweep = ctx->sched.cur_sweep;
+    h.cur_class = ctx->sched.cur_class;
+    h.cold = ctx->cold ? 1 : 0;
+    h.bytes = need;
+    std::memcpy(p, &h, sizeof(h));
+    size_t off = up8(sizeof(SnapHeader));
+    for (int i = 0; i < ctx->nimg; ++i) {
+        const Dims &d = ctx->imgs[i].d;
+        const SnapImage im{d.H, d.W, d.K, d.L};
+        std::memcpy(p + off + i * sizeof(SnapImage), &im, sizeof(im));
+    }
+    off += up8(sizeof(SnapImage) * ctx->nimg);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < ctx->nimg && e == hipSuccess; ++i) {
+        const ImageDesc &g = ctx->imgs[i];
+        const Dims &d = g.d;
+        const size_t nbins = (size_t)d.H * d.W;
+        const size_t nunits = (size_t)unit_count(d, image_level(ctx, i)) * 4;
+        const size_t nstate = ((size_t)d.K * d.hs + d.K) * 4;
+        int32_t *st0 = ctx->ar.state[0] + g.state, *st1 = ctx->ar.state[1] + g.state;
+        // pixel phases do not maintain the sizes: derive them first
+        e = launch_sizes(d, st0, st1, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p + off, ctx->ar.bins + g.bins, nbins, hipMemcpyDeviceToHost, s);
+        off += up8(nbins);
+        const int32_t *units = nullptr;
+        if (e == hipSuccess) units = units32(ctx, i, &e, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(p + off, units, nunits, hipMemcpyDeviceToHost, s);
+        off += up8(nunits);
+        if (e == hipSuccess) e = hipMemcpyAsync(p + off, st0, nstate, hipMemcpyDeviceToHost, s);
+        off += up8(nstate);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(ctx, e, "snapshot copy");
+    return check_device_flag(ctx, s);
+}
+
+seeds_status restore(seeds_ctx *ctx, const void *host, int64_t bytes, hipStream_t s) {
+    const char *p = (const char *)host;
+    if (bytes < (int64_t)sizeof(SnapHeader)) return fail(SEEDS_E_INVAL, "snapshot too short");
+    SnapHeader h;
+    std::memcpy(&h, p, sizeof(h));
+    if (h.magic != kSnapMagic) return fail(SEEDS_E_INVAL, "not a snapshot (bad magic)");
+    if (h.nimg != ctx->nimg)
+        return fail(SEEDS_E_INVAL, "snapshot holds %d images, the context %d", h.nimg, ctx->nimg);
+    if (h.B != ctx->top.B || h.I != ctx->top.I || h.gamma != ctx->top.gamma ||
+        h.rule != ctx->top.rule)
+        return fail(SEEDS_E_INVAL, "snapshot parameters (B, I, gamma, rule) differ");
+    if (bytes < (int64_t)(up8(sizeof(SnapHeader)) + up8(sizeof(SnapImage) * h.nimg)))
+        return fail(SEEDS_E_INVAL, "snapshot too short");
+    size_t off = up8(sizeof(SnapHeader));
+    for (int i = 0; i < ctx->nimg; ++i) {
+        SnapImage im;
+        std::memcpy(&im, p + off + i * sizeof(SnapImage), sizeof(im));
+        const Dims &d = ctx->imgs[i].d;
+        if (im.H != d.H || im.W != d.W || im.K != d.K || im.L != d.L)
+            return fail(SEEDS_E_INVAL, "image %d: snapshot %d x %d, K %d, L %d differs from the "
+                                       "context", i, im.W, im.H, im.K, im.L);
+    }
+    Sched sc;
+    sc.level = h.level;
+    sc.cur_level = h.cur_level;
+    sc.cur_sweep = h.cur_sweep;
+    sc.cur_class = h.cur_class;
+    if (sc.level < 0 || sc.level > ctx->top.L - 1 || sc.cur_level < -1 ||
+        sc.cur_level > sc.level || sc.cur_sweep < 0 || sc.cur_sweep > ctx->top.I ||
+        sc.cur_class < 0 || sc.cur_class > 8 || (h.cold != 0 && h.cold != 1))
+        return fail(SEEDS_E_INVAL, "snapshot cursor (%d, %d, %d, %d) is not a schedule position",
+                    sc.level, sc.cur_level, sc.cur_sweep, sc.cur_class);
+    const int64_t need = snapshot_bytes(ctx, sc.level);
+    if (h.bytes != need || bytes < need)
+        return fail(SEEDS_E_INVAL, "snapshot of %lld bytes, expected %lld", (long long)bytes,
+                    (long long)need);
+    off += up8(sizeof(SnapImage) * ctx->nimg);
+    // bins and labels index the histograms: every value is checked before
+    // anything reaches the device
+    {
+        size_t at = off;
+        for (int i = 0; i < ctx->nimg; ++i) {
+            const Dims &d = ctx->imgs[i].d;
+            const size_t nbins = (size_t)d.H * d.W;
+            const int l = std::min(sc.level, d.L - 1);
+            const size_t nunits = (size_t)unit_count(d, l);
+            const uint8_t *bp = (const uint8_t *)(p + at);
+            for (size_t q = 0; q < nbins; ++q)
+                if (bp[q] >= d.nb) return fail(SEEDS_E_INVAL, "image %d: colour bin out of range", i);
+            at += up8(nbins);
+            const int32_t *lp = (const int32_t *)(p + at);
+            for (size_t q = 0; q < nunits; ++q)
+                if (lp[q] < 0 || lp[q] >= d.K) return fail(SEEDS_E_INVAL, "image %d: label out of range", i);
+            at += up8(nunits * 4) + up8(((size_t)d.K * d.hs + d.K) * 4);
+        }
+    }
+    ctx->sched = sc;
+    ctx->cold = h.cold != 0;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < ctx->nimg && e == hipSuccess; ++i) {
+        const ImageDesc &g = ctx->imgs[i];
+        const Dims &d = g.d;
+        const size_t nbins = (size_t)d.H * d.W;
+        const size_t nunits = (size_t)unit_count(d, image_level(ctx, i)) * 4;
+        const size_t nstate = ((size_t)d.K * d.hs + d.K) * 4;
+        e = hipMemcpyAsync(ctx->ar.bins + g.bins, p + off, nbins, hipMemcpyHostToDevice, s);
+        off += up8(nbins);
+        if (e == hipSuccess) {
+            if (image_level(ctx, i) > 0)
+                e = hipMemcpyAsync(const_cast<int32_t *>(image_grid(ctx, i)), p + off, nunits,
+                                   hipMemcpyHostToDevice, s);
+            else if (ctx->ar.lab)
+                e = hipMemcpyAsync(ctx->ar.lab + g.lab, p + off, nunits, hipMemcpyHostToDevice, s);
+            else {
+                // through the staging buffer into the 16-bit plane (values
+                // checked below the superpixel count on the host)
+                e = hipMemcpyAsync(ctx->stage, p + off, nunits, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess)
+                    e = launch_narrow_labels(ctx->ar, g.lab, ctx->stage, (int64_t)d.H * d.W, s);
+            }
+        }
+        off += up8(nunits);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->ar.state[0] + g.state, p + off, nstate, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->ar.state[1] + g.state, p + off, nstate, hipMemcpyHostToDevice, s);
+        off += up8(nstate);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(ctx, e, "restore copy");
     ctx->last_stream = s;
     return SEEDS_OK;
 }
@@ -1024,6 +1277,42 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
         chosen->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
     }
     return start_schedule(ctx, s);
+}
+
+seeds_status seeds_boundary_units(const seeds_ctx *cctx, int32_t level, int32_t cls,
+                                  int64_t *units, int64_t *pixels, void *hip_stream) {
+    seeds_ctx *ctx = const_cast<seeds_ctx *>(cctx);
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    if (cls < -1 || cls > 8) return fail(SEEDS_E_INVAL, "class %d outside [-1,8]", cls);
+    if (level > ctx->sched.level)
+        return fail(SEEDS_E_INVAL, "level %d is above the context's level %d", level,
+                    ctx->sched.level);
+    if (!units && !pixels) return fail(SEEDS_E_INVAL, "both outputs are NULL");
+    return boundary_of(ctx, level, cls, units, pixels, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_snapshot_size(const seeds_ctx *ctx, int64_t *bytes) {
+    if (!bytes) return fail(SEEDS_E_INVAL, "bytes is NULL");
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    *bytes = snapshot_bytes(ctx, ctx->sched.level);
+    return SEEDS_OK;
+}
+
+seeds_status seeds_snapshot(const seeds_ctx *cctx, void *host, int64_t bytes, void *hip_stream) {
+    seeds_ctx *ctx = const_cast<seeds_ctx *>(cctx);
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    if (!host) return fail(SEEDS_E_INVAL, "snapshot buffer is NULL");
+    return snapshot(ctx, host, bytes, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_restore(seeds_ctx *ctx, const void *host, int64_t bytes, void *hip_stream) {
+    seeds_status st = check_usable(ctx);
+    if (st != SEEDS_OK) return st;
+    if (!host) return fail(SEEDS_E_INVAL, "snapshot buffer is NULL");
+    return restore(ctx, host, bytes, (hipStream_t)hip_stream);
 }
 
 const char *seeds_last_error(void) { return g_err; }

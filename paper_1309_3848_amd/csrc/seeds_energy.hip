@@ -5,6 +5,11 @@
 //        (the boundary term of Sec. 4), patches clipped at the image border.
 // For one patch, sum_k b(k)^2 is the number of ordered pairs of its cells
 // with equal labels, which needs no per-patch table.
+//
+// Test hook: boundary units of a unit grid (Sec. 5.2: a block or pixel is a
+// boundary unit when a 4-neighbour in the image carries another label; only
+// those units are proposed for a move), counted for one unit class or all,
+// with the image pixels they cover.
 #include <algorithm>
 
 #include "seeds_internal.h"
@@ -58,6 +63,30 @@ __global__ __launch_bounds__(kET) void k_energy_g(const int32_t *lab, int H, int
     add_wave(out, sum);
 }
 
+// out[0] += boundary units of class cls (cls < 0: every class) on the
+// uw x uh grid of side `side`, out[1] += the in-image pixels they cover. The
+// labels come from a grid `up` levels coarser (cw columns): unit (ux, uy)
+// carries the label of its ancestor (ux >> up, uy >> up).
+__global__ __launch_bounds__(kET) void k_boundary(const int32_t *units, int cw, int up, int uw,
+                                                  int uh, int side, int H, int W, int cls,
+                                                  unsigned long long *out) {
+    unsigned long long nu = 0, np = 0;
+    const int64_t n = (int64_t)uw * uh;
+    auto at = [&](int x, int y) { return units[(int64_t)(y >> up) * cw + (x >> up)]; };
+    for (int64_t i = (int64_t)blockIdx.x * kET + threadIdx.x; i < n; i += (int64_t)gridDim.x * kET) {
+        const int uy = (int)(i / uw), ux = (int)(i - (int64_t)uy * uw);
+        if (cls >= 0 && 3 * (uy % 3) + ux % 3 != cls) continue;
+        const int32_t k = at(ux, uy);
+        const bool boundary = (uy > 0 && at(ux, uy - 1) != k) || (uy + 1 < uh && at(ux, uy + 1) != k) ||
+                              (ux > 0 && at(ux - 1, uy) != k) || (ux + 1 < uw && at(ux + 1, uy) != k);
+        if (!boundary) continue;
+        nu += 1;
+        np += (unsigned long long)(min(side, W - ux * side) * min(side, H - uy * side));
+    }
+    add_wave(out, nu);
+    add_wave(out + 1, np);
+}
+
 int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + kET - 1) / kET)); }
 
 }  // namespace
@@ -72,6 +101,15 @@ hipError_t launch_energy(const int32_t *hist, const Dims &d, const int32_t *lab,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_energy_g, dim3(grid_for((int64_t)d.H * d.W)), dim3(kET), 0, s, lab, d.H,
                        d.W, out + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary(const int32_t *units, const Dims &d, int units_level, int level,
+                           int cls, unsigned long long *out, hipStream_t s) {
+    const int uw = units_w(d, level), uh = units_h(d, level);
+    hipLaunchKernelGGL(k_boundary, dim3(grid_for((int64_t)uw * uh)), dim3(kET), 0, s, units,
+                       units_w(d, units_level), units_level - level, uw, uh, 1 << level, d.H, d.W,
+                       cls, out);
     return hipGetLastError();
 }
 

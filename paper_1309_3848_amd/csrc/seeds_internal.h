@@ -95,10 +95,16 @@ struct ImageDesc {
     int64_t pend;      // element offset into the decision arena (largest class)
 };
 
+// Pixel labels are stored as 16-bit values when every image of a context has
+// at most kLab16MaxK superpixels (labels 0 .. 65534), halving the bytes the
+// pixel phases read; otherwise as int32. Block grids are always int32.
+constexpr int kLab16MaxK = 65535;
+
 // Arenas of a context.
 struct Arenas {
     uint8_t *bins;
-    int32_t *lab;
+    int32_t *lab;       // pixel labels (int32), or nullptr when lab16 is used
+    uint16_t *lab16;    // pixel labels (16-bit), or nullptr
     int32_t *bl;
     int32_t *state[2];  // two equal copies between launches; phases alternate them
     int32_t *src;       // phase stamps of move sources (exact rule's drop rule)
@@ -239,6 +245,12 @@ hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // spread over the whole device (a runtime copy when src is not 16-byte
 // aligned).
 hipError_t launch_copy(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
+// n pixel labels of an arena (int32 or 16-bit, at element offset `at`) to
+// int32 device memory, over the whole device.
+hipError_t launch_copy_labels(int32_t *dst, const Arenas &a, int64_t at, int64_t n, hipStream_t s);
+// n int32 labels (values < 65536) into the 16-bit plane at element offset at.
+hipError_t launch_narrow_labels(const Arenas &a, int64_t at, const int32_t *src, int64_t n,
+                                hipStream_t s);
 hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                        int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
                        const int64_t *pitch_table, int groups, hipStream_t s);
@@ -303,9 +315,47 @@ __host__ __device__ inline int zero_groups(const Dims &d) {
 hipError_t launch_energy(const int32_t *hist, const Dims &d, const int32_t *lab,
                          unsigned long long *out, hipStream_t s);
 
+// Test hook: out[0] += the boundary units of class cls (< 0: all classes) on
+// the unit grid of `level` of an image, out[1] += the pixels they cover (out
+// is not cleared here). `units` is the image's grid of units_level >= level;
+// finer units take their ancestor's label.
+hipError_t launch_boundary(const int32_t *units, const Dims &d, int units_level, int level,
+                           int cls, unsigned long long *out, hipStream_t s);
+
 // Copy n int32 from 16-byte-aligned device memory to device-visible pinned
 // host memory (dst is the device-side address) with a few workgroups.
 hipError_t launch_copy_out(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
+
+// Workgroups of one launch: the map (device array of (image, rank) per
+// logical workgroup; nullptr for a single image) and their number.
+struct LaunchMap {
+    const int2 *map = nullptr;
+    int groups = 0;
+};
+
+// What the per-phase schedule needs of a context. phase_map ([level * 9 +
+// cls]) and descend_map ([level]) are nullptr for a single image, whose
+// launch shapes follow from `one`.
+struct ScheduleArgs {
+    BatchArgs b;
+    ImageDesc one;
+    Dims top;  // shared parameters; L = the most levels of any image
+    const LaunchMap *phase_map = nullptr;
+    const LaunchMap *descend_map = nullptr;
+    int64_t src_elems = 0;
+    PhaseTuning tune;
+};
+
+// Enqueue the schedule from the cursor `sched` as per-phase launches (at most
+// max_phases phases; < 0: all), ending with the replay that makes both state
+// copies equal again; advances the cursor. *done (may be NULL) receives the
+// phases enqueued.
+hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_phases,
+                            int32_t *done, hipStream_t s);
+
+// Argument checks of seeds_init (every SEEDS_E_INVAL case) and the image's
+// dimensions and grid.
+seeds_status check_params(int32_t H, int32_t W, int32_t K, const seeds_params *p, Dims *d);
 
 // Persistent cooperative refinement of a single image.
 hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const PersistentGeom &g,

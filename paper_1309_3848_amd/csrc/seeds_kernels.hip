@@ -45,8 +45,8 @@ struct InitSlots {
 // One tile of one image. st0 / st1: the image's state in both copies.
 __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
                           uint8_t *__restrict__ bins, int32_t *__restrict__ top,
-                          int32_t *__restrict__ st0, int32_t *__restrict__ st1, int tile,
-                          InitSlots &sl) {
+                          uint16_t *__restrict__ top16, int32_t *__restrict__ st0,
+                          int32_t *__restrict__ st1, int tile, InitSlots &sl) {
     const int64_t khs = (int64_t)d.K * d.hs;
     const int bw = (d.W + d.T - 1) / d.T, bh = (d.H + d.T - 1) / d.T;
     const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
@@ -92,7 +92,12 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
         bins[(int64_t)y * d.W + x] = (uint8_t)j;
         const int sy = sl.row[r];
         const int label = sy * d.gx + sx;
-        if (((x | y) & (d.T - 1)) == 0) top[(int64_t)(y >> sh) * bw + (x >> sh)] = label;
+        if (((x | y) & (d.T - 1)) == 0) {
+            if (top16)
+                top16[(int64_t)(y >> sh) * bw + (x >> sh)] = (uint16_t)label;
+            else
+                top[(int64_t)(y >> sh) * bw + (x >> sh)] = label;
+        }
         if (local) {
             const int slot = (sy - sy_lo) * nsx + (sx - sx_lo);
             atomicAdd(&dyn_hist[slot * d.hs + j], 1);
@@ -131,9 +136,10 @@ __device__ __forceinline__ void init_image(const BatchArgs &b, const ImageDesc &
                                            InitSlots &sl) {
     const Dims &d = g.d;
     // the top blocks' grid (level L-1) lives in block-grid buffer (L-1) % 2;
-    // with one level the top blocks are the pixels
-    int32_t *top = d.L > 1 ? b.ar.bl + g.bl[(d.L - 1) & 1] : b.ar.lab + g.lab;
-    init_tile(d, rgb, pitch, b.ar.bins + g.bins, top, b.ar.state[0] + g.state,
+    // with one level the top blocks are the pixels (int32 or 16-bit plane)
+    int32_t *top = d.L > 1 ? b.ar.bl + g.bl[(d.L - 1) & 1] : (b.ar.lab ? b.ar.lab + g.lab : nullptr);
+    uint16_t *top16 = d.L == 1 && b.ar.lab16 ? b.ar.lab16 + g.lab : nullptr;
+    init_tile(d, rgb, pitch, b.ar.bins + g.bins, top, top16, b.ar.state[0] + g.state,
               b.ar.state[1] + g.state, tile, sl);
 }
 
@@ -208,8 +214,9 @@ __device__ __forceinline__ int rehist_entry(RehistLds &r, int32_t k, bool insert
 
 constexpr int kRehistPx = kInitTW * kInitTH / kThreads;  // pixels per thread
 
+template <typename LabT>
 __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
-                            uint8_t *__restrict__ bins, const int32_t *__restrict__ lab,
+                            uint8_t *__restrict__ bins, const LabT *__restrict__ lab,
                             int32_t *__restrict__ st0, int32_t *__restrict__ st1, int tile,
                             RehistLds &r) {
     const int64_t khs = (int64_t)d.K * d.hs;
@@ -235,7 +242,7 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
         c0[q] = p[0];
         c1[q] = p[1];
         c2[q] = p[2];
-        k[q] = lab[(int64_t)yc * d.W + xc];
+        k[q] = (int32_t)lab[(int64_t)yc * d.W + xc];
     }
     const int lane = threadIdx.x & 63;
     // the wavefront's last four (label, entry) pairs: the rows of one thread
@@ -330,6 +337,14 @@ __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int6
     }
 }
 
+template <typename LabT>
+__device__ __forceinline__ const LabT *rehist_plane(const Arenas &a);
+template <>
+__device__ __forceinline__ const int32_t *rehist_plane<int32_t>(const Arenas &a) { return a.lab; }
+template <>
+__device__ __forceinline__ const uint16_t *rehist_plane<uint16_t>(const Arenas &a) { return a.lab16; }
+
+template <typename LabT>
 __global__ __launch_bounds__(kThreads) void k_rehist(BatchArgs b, ImageDesc one,
                                                      const uint8_t *rgb_one, int64_t pitch_one,
                                                      const int2 *map,
@@ -337,15 +352,32 @@ __global__ __launch_bounds__(kThreads) void k_rehist(BatchArgs b, ImageDesc one,
                                                      const int64_t *pitch_table) {
     __shared__ RehistLds r;
     const int lg = xcd_group();
+    const LabT *lab = rehist_plane<LabT>(b.ar);
     if (b.nimg == 1) {
-        rehist_tile(one.d, rgb_one, pitch_one, b.ar.bins, b.ar.lab, b.ar.state[0],
-                    b.ar.state[1], lg, r);
+        rehist_tile(one.d, rgb_one, pitch_one, b.ar.bins, lab, b.ar.state[0], b.ar.state[1], lg,
+                    r);
         return;
     }
     const int2 e = map[lg];
     const ImageDesc g = b.imgs[e.x];
-    rehist_tile(g.d, rgb_table[e.x], pitch_table[e.x], b.ar.bins + g.bins, b.ar.lab + g.lab,
+    rehist_tile(g.d, rgb_table[e.x], pitch_table[e.x], b.ar.bins + g.bins, lab + g.lab,
                 b.ar.state[0] + g.state, b.ar.state[1] + g.state, e.y, r);
+}
+
+// 16-bit pixel labels to int32 and back (readback, snapshots), over the
+// whole device.
+__global__ __launch_bounds__(kThreads) void k_widen(int32_t *__restrict__ dst,
+                                                    const uint16_t *__restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+        dst[i] = (int32_t)src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_narrow(uint16_t *__restrict__ dst,
+                                                     const int32_t *__restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+        dst[i] = (uint16_t)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -411,8 +443,32 @@ hipError_t launch_init_mixed(const BatchArgs &b, const TickList &l, int groups, 
 hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                          int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
                          const int64_t *pitch_table, int groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_rehist, dim3(groups), dim3(kThreads), kRehistSlots * one.d.hs * 4, s, b,
-                       one, rgb_one, pitch_one, map, rgb_table, pitch_table);
+    if (b.ar.lab16)
+        hipLaunchKernelGGL(k_rehist<uint16_t>, dim3(groups), dim3(kThreads),
+                           kRehistSlots * one.d.hs * 4, s, b, one, rgb_one, pitch_one, map,
+                           rgb_table, pitch_table);
+    else
+        hipLaunchKernelGGL(k_rehist<int32_t>, dim3(groups), dim3(kThreads),
+                           kRehistSlots * one.d.hs * 4, s, b, one, rgb_one, pitch_one, map,
+                           rgb_table, pitch_table);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_labels(int32_t *dst, const Arenas &a, int64_t at, int64_t n, hipStream_t s) {
+    if (!a.lab16) return launch_copy(dst, a.lab + at, n, s);
+    if (n <= 0) return hipSuccess;
+    const unsigned want = blocks_for(n, kThreads);
+    hipLaunchKernelGGL(k_widen, dim3(want > 8192u ? 8192u : want), dim3(kThreads), 0, s, dst,
+                       a.lab16 + at, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow_labels(const Arenas &a, int64_t at, const int32_t *src, int64_t n,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned want = blocks_for(n, kThreads);
+    hipLaunchKernelGGL(k_narrow, dim3(want > 8192u ? 8192u : want), dim3(kThreads), 0, s,
+                       a.lab16 + at, src, n);
     return hipGetLastError();
 }
 

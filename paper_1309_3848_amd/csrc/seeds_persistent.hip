@@ -66,7 +66,7 @@ struct RefineLaunch {
     uint32_t stamp;  // stamp of the phase before the first one of the launch
 };
 
-template <bool BIG>
+template <bool BIG, typename LabT>
 __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
     extern __shared__ uint8_t sbin[];
     __shared__ DeltaTable t;
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
             if (phases > 0) replay(prev_log, min(prev_n, b.log_cap), W);
             ++stamp;
             if (sc.level == 0) {
-                pixel_phase<true>(b, v, cls, par, t, cur_log, pl);
+                pixel_phase<true, LabT>(b, v, cls, par, t, cur_log, pl);
             } else if (d.rule == SEEDS_BLOCK_EXACT) {
                 block_phase_any<BIG>(b, v, sc.level, cls, par, 1, stamp, sbin, t, cur_log);
                 if (!grid_sync(sync, gen)) return;
@@ -134,7 +134,9 @@ PersistentGeom persistent_geometry(const Dims &d, int device, int groups_per_cu)
         cus < 1)
         cus = 1;
     int occ = 0;
-    const void *fn = d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    // (the 16-bit variants use no more resources than these)
+    const void *fn = d.L > 4 ? (const void *)k_refine<true, int32_t>
+                             : (const void *)k_refine<false, int32_t>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kPT, g.lds_bytes) != hipSuccess ||
         occ < 1)
         occ = 1;
@@ -164,7 +166,11 @@ hipError_t launch_refine(const BatchArgs &b, const ImageDesc &one, const Persist
     a.max_phases = max_phases;
     a.stamp = stamp;
     void *args[] = {&a};
-    const void *fn = one.d.L > 4 ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    const void *fn;
+    if (b.ar.lab16)
+        fn = one.d.L > 4 ? (const void *)k_refine<true, uint16_t> : (const void *)k_refine<false, uint16_t>;
+    else
+        fn = one.d.L > 4 ? (const void *)k_refine<true, int32_t> : (const void *)k_refine<false, int32_t>;
     return hipLaunchCooperativeKernel(fn, dim3(g.groups), dim3(kPT), args, (unsigned)g.lds_bytes,
                                       s);
 }

@@ -26,6 +26,8 @@
 // next launch can add them.
 #pragma once
 
+#include <type_traits>
+
 #include "seeds_device.h"
 
 namespace seeds {
@@ -35,7 +37,8 @@ constexpr int kPT = kPersistentThreads;
 struct ImageView {
     Dims d;
     const uint8_t *bins;
-    int32_t *lab;
+    int32_t *lab;        // pixel labels: int32 plane, or
+    uint16_t *lab16;     // the 16-bit plane (exactly one is non-null)
     int32_t *bl;         // block grid buffer 0 of this image; level l is in
     int64_t bl_step;     // buffer l % 2, at bl + (l % 2) * bl_step
     int64_t base;        // global index of this image's state in a state copy
@@ -56,7 +59,8 @@ __device__ __forceinline__ ImageView make_view(const BatchArgs &b, const ImageDe
     ImageView v;
     v.d = g.d;
     v.bins = b.ar.bins + g.bins;
-    v.lab = b.ar.lab + g.lab;
+    v.lab = b.ar.lab ? b.ar.lab + g.lab : nullptr;
+    v.lab16 = b.ar.lab16 ? b.ar.lab16 + g.lab : nullptr;
     v.bl = b.ar.bl + g.bl[0];
     v.bl_step = g.bl[1] - g.bl[0];
     v.base = g.state;
@@ -76,6 +80,7 @@ __device__ __forceinline__ ImageView single_view(const BatchArgs &b, const Image
     v.d = g.d;
     v.bins = b.ar.bins;
     v.lab = b.ar.lab;
+    v.lab16 = b.ar.lab16;
     v.bl = b.ar.bl;
     v.bl_step = g.bl[1];
     v.base = 0;
@@ -85,6 +90,15 @@ __device__ __forceinline__ ImageView single_view(const BatchArgs &b, const Image
     v.ngroups = ngroups;
     return v;
 }
+
+// The pixel-label plane of a view as the type the kernel variant was built
+// for.
+template <typename LabT>
+__device__ __forceinline__ LabT *label_plane(const ImageView &v);
+template <>
+__device__ __forceinline__ int32_t *label_plane<int32_t>(const ImageView &v) { return v.lab; }
+template <>
+__device__ __forceinline__ uint16_t *label_plane<uint16_t>(const ImageView &v) { return v.lab16; }
 
 // Pointer selection by a run-time index without indexing an array (which would
 // put the array in scratch memory).
@@ -192,10 +206,11 @@ __device__ __forceinline__ void wave_append(PixelTile &pt, bool take, int value)
     if (take) pt.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
 }
 
-template <bool COMPACT = true>
+template <bool COMPACT = true, typename LabT = int32_t>
 __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int cls, int par,
                                    DeltaTable &t, int2 *mylog, PixelTile &pt) {
     const Dims &d = v.d;
+    LabT *const lab = label_plane<LabT>(v);
     const int cx = cls % 3, cy = cls / 3;
     const int ncx = class_cols(d.W, cls), ncy = class_rows(d.H, cls);
     const int ntx = (ncx + kPixTX - 1) / kPixTX;
@@ -207,7 +222,7 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
                   "the window load covers 3 kPixTX + 2 columns with four wavefronts");
     // one pixel's move: its label in place, its count from k to n
     auto apply = [&](int x, int y, int j, const PixelMove &mv) {
-        v.lab[(int64_t)y * d.W + x] = mv.n;
+        lab[(int64_t)y * d.W + x] = (LabT)mv.n;
         table_add(b, t, W, mylog, (int32_t)(v.base + mv.n * d.hs + j), 1);
         table_add(b, t, W, mylog, (int32_t)(v.base + mv.k * d.hs + j), -1);
     };
@@ -240,7 +255,7 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
             if (wide) {
 #pragma unroll
                 for (int r = 0; r < kWinH; ++r)
-                    cell[r] = v.lab[(int64_t)min(max(y0 - 2 + r, 0), d.H - 1) * d.W + xc];
+                    cell[r] = lab[(int64_t)min(max(y0 - 2 + r, 0), d.H - 1) * d.W + xc];
 #pragma unroll
                 for (int r = 0; r < kWinH; ++r) {
                     const int yy = y0 - 2 + r;
@@ -248,7 +263,7 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
                 }
             } else {
                 const int yy = y0 - 2 + min(wr, kWinH - 1);
-                cell[0] = v.lab[(int64_t)min(max(yy, 0), d.H - 1) * d.W + xc];
+                cell[0] = lab[(int64_t)min(max(yy, 0), d.H - 1) * d.W + xc];
                 if (!(in_x && yy >= 0 && yy < d.H)) cell[0] = -1;
             }
         } else {
@@ -257,12 +272,12 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
 #pragma unroll
                 for (int r = 0; r < kWinH; ++r) {
                     const int yy = y0 - 2 + r;
-                    cell[r] = (in_x && yy >= 0 && yy < d.H) ? v.lab[(int64_t)yy * d.W + xx] : -1;
+                    cell[r] = (in_x && yy >= 0 && yy < d.H) ? (int)lab[(int64_t)yy * d.W + xx] : -1;
                 }
             } else {
                 const int yy = y0 - 2 + wr;
                 cell[0] = (wr < kWinH && in_x && yy >= 0 && yy < d.H)
-                              ? v.lab[(int64_t)yy * d.W + xx]
+                              ? (int)lab[(int64_t)yy * d.W + xx]
                               : -1;
             }
         }
@@ -582,6 +597,8 @@ __device__ inline void descend(const ImageView &v, int level) {
     const Dims &d = v.d;
     const int fw = units_w(d, level), fh = units_h(d, level);
     const int32_t *from = level_grid(v, level);
+    // into the pixel labels from level 1 (16-bit plane: to16)
+    uint16_t *to16 = level == 1 ? v.lab16 : nullptr;
     int32_t *to = level == 1 ? v.lab : level_grid(v, level - 1);
     const int tw = units_w(d, level - 1), th = units_h(d, level - 1);
     // work item = (parent row, chunk of kPT parents): each thread copies one
@@ -593,13 +610,19 @@ __device__ inline void descend(const ImageView &v, int level) {
         if (px >= fw) continue;
         const int32_t l = from[(int64_t)py * fw + px];
         const int x = 2 * px, y = 2 * py;  // x < tw and y < th: the child grid is 2f-1 or 2f wide
-        int32_t *row = to + (int64_t)y * tw + x;
-        row[0] = l;
-        if (x + 1 < tw) row[1] = l;
-        if (y + 1 < th) {
-            row[tw] = l;
-            if (x + 1 < tw) row[tw + 1] = l;
-        }
+        auto put = [&](auto *row) {
+            using T = typename std::remove_pointer<decltype(row)>::type;
+            row[0] = (T)l;
+            if (x + 1 < tw) row[1] = (T)l;
+            if (y + 1 < th) {
+                row[tw] = (T)l;
+                if (x + 1 < tw) row[tw + 1] = (T)l;
+            }
+        };
+        if (to16)
+            put(to16 + (int64_t)y * tw + x);
+        else
+            put(to + (int64_t)y * tw + x);
     }
 }
 

@@ -35,7 +35,7 @@ struct PhaseWork {
 // it runs after the replay prefetch is issued so that the two overlap.
 // KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
 // workgroup from its work).
-template <bool BIG, int KINDS, bool COMPACT, typename Find>
+template <bool BIG, int KINDS, bool COMPACT, typename LabT, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups,
                                            int slot_base = 0) {
@@ -62,12 +62,12 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     const int64_t my_slot = (int64_t)par * b.log_groups + slot_base + blockIdx.x;
     int2 *mylog = b.ar.log + my_slot * b.log_cap;
     if constexpr (KINDS == 1) {
-        pixel_phase<COMPACT>(b, w.v, w.cls, par, t, mylog, pl);
+        pixel_phase<COMPACT, LabT>(b, w.v, w.cls, par, t, mylog, pl);
     } else if constexpr (KINDS == 2) {
         block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     } else {
         if (w.level == 0)
-            pixel_phase<COMPACT>(b, w.v, w.cls, par, t, mylog, pl);
+            pixel_phase<COMPACT, LabT>(b, w.v, w.cls, par, t, mylog, pl);
         else
             block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     }
@@ -92,14 +92,15 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
 
 // PIXEL selects the pixel-level or the block-level code: each variant holds
 // only its own registers, and the block variant of the common hierarchies
-// (BIG = false) fits six wavefronts per SIMD without spilling.
+// (BIG = false) fits six wavefronts per SIMD without spilling. L16: pixel
+// labels stored as 16-bit values (pixel variants only).
 // Tuning (mapping only, never the moves): COMPACT for pixel phases, and
 // `remap` = 1 numbers the workgroups so that each XCD works a contiguous band.
-template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT>
+template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT, bool L16 = false>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
     uint32_t stamp, int replay_groups, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, typename std::conditional<L16, uint16_t, int32_t>::type>(
         b,
         [&]() {
             return PhaseWork{resolve<BATCH>(b, one, map, level, cls, remap), level, cls};
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
 template <bool BIG, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, int32_t>(
         b,
         [&]() {
             const int lg = remap ? xcd_group() : (int)blockIdx.x;
@@ -170,7 +171,13 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
     const int lds = phase_lds_bytes(level, one.d.hs);
     const bool batch = b.nimg > 1;
     decltype(&k_phase<false, false, true, true>) fn;
-    if (level == 0) {
+    if (level == 0 && b.ar.lab16) {
+        if (tune.pixel_compact)
+            fn = batch ? k_phase<false, true, true, true, true> : k_phase<false, false, true, true, true>;
+        else
+            fn = batch ? k_phase<false, true, true, false, true>
+                       : k_phase<false, false, true, false, true>;
+    } else if (level == 0) {
         if (tune.pixel_compact)
             fn = batch ? k_phase<false, true, true, true> : k_phase<false, false, true, true>;
         else

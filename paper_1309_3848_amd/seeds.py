@@ -117,6 +117,12 @@ def lib() -> ctypes.CDLL:
             "seeds_set_tuning": ([P, ctypes.POINTER(seeds_tuning)], S),
             "seeds_autotune": ([P, I32, ctypes.POINTER(seeds_tuning),
                                 ctypes.POINTER(ctypes.c_float), P], S),
+            "seeds_boundary_units": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P],
+                                     S),
+            "seeds_snapshot_size": ([P, ctypes.POINTER(I64)], S),
+            "seeds_snapshot": ([P, P, I64, P], S),
+            "seeds_restore": ([P, P, I64, P], S),
+            "seeds_lds_atomic_rate": ([ctypes.POINTER(ctypes.c_double), P], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -310,6 +316,30 @@ def seeds_batch_energy(ctx, image: int, stream=None) -> tuple:
     return h.value, g.value
 
 
+def seeds_boundary_units(ctx, cls: int = -1, level: int = -1, stream=None):
+    """Per image: (boundary units, pixels they cover) of class cls (-1: all)
+    on the unit grid of `level` (-1: the image's current level)."""
+    n = seeds_batch_count(ctx)
+    units = (ctypes.c_int64 * max(n, 1))()
+    pixels = (ctypes.c_int64 * max(n, 1))()
+    _check(lib().seeds_boundary_units(ctx, level, cls, units, pixels, _stream(stream)))
+    return [(units[i], pixels[i]) for i in range(n)]
+
+
+def seeds_snapshot(ctx, stream=None) -> bytes:
+    """The context's whole state (bins, labels, histograms, sizes, cursor)."""
+    n = ctypes.c_int64()
+    _check(lib().seeds_snapshot_size(ctx, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().seeds_snapshot(ctx, buf, n.value, _stream(stream)))
+    return buf.raw
+
+
+def seeds_restore(ctx, snap: bytes, stream=None) -> None:
+    buf = ctypes.create_string_buffer(snap, len(snap))
+    _check(lib().seeds_restore(ctx, buf, len(snap), _stream(stream)))
+
+
 def seeds_set_launch_mode(ctx, mode: int) -> None:
     _check(lib().seeds_set_launch_mode(ctx, mode))
 
@@ -407,6 +437,13 @@ def seeds_autotune(ctx, reps: int = 3, stream=None):
     _check(lib().seeds_autotune(ctx, reps, ctypes.byref(t), ms, _stream(stream)))
     return ({"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap},
             [ms[i] for i in range(4)])
+
+
+def seeds_lds_atomic_rate(stream=None) -> float:
+    """Measured LDS-atomic throughput, G wavefront instructions per second."""
+    r = ctypes.c_double()
+    _check(lib().seeds_lds_atomic_rate(ctypes.byref(r), _stream(stream)))
+    return r.value
 
 
 def seeds_last_error() -> str:

@@ -235,3 +235,4 @@ def test_tuning_argument_checks(S):
     assert L.seeds_get_tuning(None, ctypes.byref(t)) == S.SEEDS_E_INVAL
     assert L.seeds_set_tuning(None, ctypes.byref(t)) == S.SEEDS_E_INVAL
     assert L.seeds_autotune(None, 3, None, None, None) == S.SEEDS_E_INVAL
+
