@@ -428,6 +428,21 @@ seeds_status seeds_lds_atomic_rate(double *ginst_per_s, void *hip_stream);
  * it last used). NULL is accepted.                                            */
 seeds_status seeds_destroy(seeds_ctx *ctx);
 
+/* ---- Fault injection (tests of the error paths) ---------------------------
+ * Make the library's own code fail on purpose, on the host, without touching
+ * the device: after `after` more operations of `kind`, the next one reports a
+ * failure instead of running (after < 0 disarms; the setting is global to
+ * the process and used once). SEEDS_FAULT_ALLOC: the device allocation of
+ * seeds_init / seeds_batch_init / seeds_server_create fails as if out of
+ * memory (SEEDS_E_NOMEM, nothing is leaked). SEEDS_FAULT_LAUNCH: a kernel
+ * launch of a context (initialisation, a phase, a level transition, a warm
+ * start) or of a server tick fails; the call returns SEEDS_E_DEVICE and the
+ * context or server is poisoned, as after a real launch failure.            */
+#define SEEDS_FAULT_ALLOC 0
+#define SEEDS_FAULT_LAUNCH 1
+
+seeds_status seeds_debug_inject_fault(int32_t kind, int32_t after);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *seeds_last_error(void);
 

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <utility>
 #include <vector>
@@ -35,6 +36,20 @@ seeds_status set_error(seeds_status st, const char *fmt, ...) {
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
     return st;
+}
+
+// Operations of each kind still allowed before an injected failure (< 0: none
+// armed). Decremented by every operation of that kind while armed.
+std::atomic<int> g_fault_after[2] = {{-1}, {-1}};
+
+bool inject_fault(int kind) {
+    if (kind < 0 || kind > 1) return false;
+    int left = g_fault_after[kind].load(std::memory_order_relaxed);
+    while (left >= 0) {
+        if (g_fault_after[kind].compare_exchange_weak(left, left - 1, std::memory_order_relaxed))
+            return left == 0;
+    }
+    return false;
 }
 
 }  // namespace seeds
@@ -205,7 +220,9 @@ const int32_t *image_grid(const seeds_ctx *ctx, int i) {
 seeds_status start_schedule(seeds_ctx *ctx, hipStream_t s) {
     const LaunchMap m = init_launch(ctx);
     // both state copies (histograms, then sizes, of every image) are contiguous
-    hipError_t e = launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
+    hipError_t e = inject_fault(SEEDS_FAULT_LAUNCH)
+                       ? hipErrorLaunchFailure
+                       : launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
     if (e == hipSuccess)
         e = launch_init(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
                         ctx->d_rgb, ctx->d_pitch, m.groups, s);
@@ -242,6 +259,7 @@ hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_pha
         int cls = 0;
         const SchedOp op = sched_next(top, sched, max_phases < 0 ? -1 : max_phases - done, &cls);
         if (op == OP_END) break;
+        if (inject_fault(SEEDS_FAULT_LAUNCH)) return hipErrorLaunchFailure;
         if (op == OP_DESCEND) {
             const LaunchMap m = a.phase_map ? a.descend_map[sched.level]
                                             : LaunchMap{nullptr, descend_groups(one.d, sched.level)};
@@ -367,8 +385,9 @@ seeds_status run_schedule(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out,
             ++ops;
         }
         if (ops) {
-            hipError_t e = hipSuccess;
-            if (top.rule == SEEDS_BLOCK_EXACT) e = launch_fill(ctx->ar.src, 0, ctx->src_elems, s);
+            hipError_t e = inject_fault(SEEDS_FAULT_LAUNCH) ? hipErrorLaunchFailure : hipSuccess;
+            if (e == hipSuccess && top.rule == SEEDS_BLOCK_EXACT)
+                e = launch_fill(ctx->ar.src, 0, ctx->src_elems, s);
             if (e == hipSuccess)
                 e = launch_refine(batch_args(ctx), ctx->imgs[0], ctx->geom, start, max_phases, 0, s);
             if (e != hipSuccess) return device_error(ctx, e, "persistent refine launch");
@@ -544,7 +563,7 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
         destroy_ctx(ctx);
         return fail(SEEDS_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     }
-    e = hipMalloc(&ctx->slab, off);
+    e = inject_fault(SEEDS_FAULT_ALLOC) ? hipErrorOutOfMemory : hipMalloc(&ctx->slab, off);
     if (e != hipSuccess) {
         ctx->slab = nullptr;
         (void)hipGetLastError();
@@ -781,7 +800,9 @@ seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t
     st = set_images(ctx, rgb, pitch, s);
     if (st != SEEDS_OK) return st;
     const LaunchMap m = init_launch(ctx);
-    hipError_t e = launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
+    hipError_t e = inject_fault(SEEDS_FAULT_LAUNCH)
+                       ? hipErrorLaunchFailure
+                       : launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
     if (e == hipSuccess)
         e = launch_rehist(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
                           ctx->d_rgb, ctx->d_pitch, m.groups, s);
@@ -1313,6 +1334,13 @@ seeds_status seeds_restore(seeds_ctx *ctx, const void *host, int64_t bytes, void
     if (st != SEEDS_OK) return st;
     if (!host) return fail(SEEDS_E_INVAL, "snapshot buffer is NULL");
     return restore(ctx, host, bytes, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_debug_inject_fault(int32_t kind, int32_t after) {
+    if (kind != SEEDS_FAULT_ALLOC && kind != SEEDS_FAULT_LAUNCH)
+        return fail(SEEDS_E_INVAL, "unknown fault kind %d", kind);
+    g_fault_after[kind].store(after < 0 ? -1 : after, std::memory_order_relaxed);
+    return SEEDS_OK;
 }
 
 const char *seeds_last_error(void) { return g_err; }

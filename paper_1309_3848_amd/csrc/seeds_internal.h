@@ -19,6 +19,11 @@ namespace seeds {
 // return st.
 seeds_status set_error(seeds_status st, const char *fmt, ...);
 
+// Fault injection (seeds_debug_inject_fault): true when the next operation of
+// this kind must fail instead of running. kind: SEEDS_FAULT_ALLOC for device
+// allocations, SEEDS_FAULT_LAUNCH for kernel launches of contexts and servers.
+bool inject_fault(int kind);
+
 // Histogram rows are padded so every row starts on a 32-byte boundary.
 __host__ __device__ inline int hist_stride(int nbins) { return (nbins + 7) & ~7; }
 

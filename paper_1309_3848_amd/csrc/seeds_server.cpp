@@ -266,7 +266,8 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
     const size_t o_log = take(2 * (size_t)sv->g_cap * sv->log_cap * 8);
     const size_t o_logn = take(2 * (size_t)sv->g_cap * 4), o_sync = take(16), o_dummy = take(256);
     const size_t o_ring = take(kRing * sv->ring_bytes);
-    if (e == hipSuccess) e = hipMalloc(&sv->slab, off);
+    if (e == hipSuccess)
+        e = inject_fault(SEEDS_FAULT_ALLOC) ? hipErrorOutOfMemory : hipMalloc(&sv->slab, off);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->ring_host, kRing * sv->ring_bytes, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->flag_host, 64, 0);
     if (e == hipSuccess) *sv->flag_host = 0;
@@ -514,6 +515,7 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
         e = hipMemcpyAsync((void *)dev_coarse, coarse_host, ncoarse_used * sizeof(int32_t),
                            hipMemcpyHostToDevice, s);
     const BatchArgs b = server_args(sv);
+    if (e == hipSuccess && n > 0 && inject_fault(SEEDS_FAULT_LAUNCH)) e = hipErrorLaunchFailure;
     if (e == hipSuccess && zero_groups_total > 0)
         e = launch_zero_mixed(b, zero_l, zero_groups_total, s);
     if (e == hipSuccess && init_groups_total > 0)

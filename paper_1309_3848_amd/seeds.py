@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
             "seeds_snapshot": ([P, P, I64, P], S),
             "seeds_restore": ([P, P, I64, P], S),
             "seeds_lds_atomic_rate": ([ctypes.POINTER(ctypes.c_double), P], S),
+            "seeds_debug_inject_fault": ([I32, I32], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
         }
@@ -444,6 +445,16 @@ def seeds_lds_atomic_rate(stream=None) -> float:
     r = ctypes.c_double()
     _check(lib().seeds_lds_atomic_rate(ctypes.byref(r), _stream(stream)))
     return r.value
+
+
+SEEDS_FAULT_ALLOC = 0
+SEEDS_FAULT_LAUNCH = 1
+
+
+def seeds_debug_inject_fault(kind: int, after: int) -> None:
+    """Test hook: the operation of `kind` after `after` more ones fails (on the
+    host; nothing runs on the device); after < 0 disarms."""
+    _check(lib().seeds_debug_inject_fault(kind, after))
 
 
 def seeds_last_error() -> str:

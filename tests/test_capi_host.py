@@ -236,3 +236,10 @@ def test_tuning_argument_checks(S):
     assert L.seeds_set_tuning(None, ctypes.byref(t)) == S.SEEDS_E_INVAL
     assert L.seeds_autotune(None, 3, None, None, None) == S.SEEDS_E_INVAL
 
+
+def test_fault_injection_argument_checks(S):
+    L = S.lib()
+    assert L.seeds_debug_inject_fault(2, 0) == S.SEEDS_E_INVAL
+    assert L.seeds_debug_inject_fault(-1, 0) == S.SEEDS_E_INVAL
+    assert L.seeds_debug_inject_fault(S.SEEDS_FAULT_ALLOC, -1) == S.SEEDS_OK
+    assert L.seeds_debug_inject_fault(S.SEEDS_FAULT_LAUNCH, -1) == S.SEEDS_OK
