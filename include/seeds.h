@@ -415,6 +415,34 @@ seeds_status seeds_quality_metrics(const int32_t *labels, const int32_t *truth, 
                                    int32_t W, int32_t num_labels, int32_t num_truth, int32_t eps,
                                    seeds_quality *out, void *hip_stream);
 
+/* ---- Allocation-free refinement -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc. One call does
+ * what seeds_init, seeds_refine (the whole schedule), seeds_labels to device
+ * memory and seeds_destroy do together, with the same kernels and the same
+ * result, but every buffer beyond rgb and labels_out lives in a fixed device
+ * array of SEEDS_NOALLOC_MAX_BYTES that the library holds on each device it
+ * runs on until the process ends. The call allocates nothing (no hipMalloc,
+ * no graph, no stream) and only enqueues kernels on hip_stream; it returns
+ * before they complete.
+ *   rgb, H, W, row_pitch_bytes, num_superpixels, p  as for seeds_init;
+ *   labels_out  device pointer to H x W int32 (row-major, values in
+ *               [0, K_eff)), written in stream order.
+ * SEEDS_E_INVAL (before any device work) for the arguments seeds_init
+ * refuses, NULL pointers, and images whose state does not fit the array
+ * (a 1920 x 1080 image with 4 levels and B = 5 needs about 25 MB; the two
+ * histogram copies take about 1 KB per superpixel at B = 5; the text names
+ * the bytes needed). The first call on a device resolves the array's
+ * address there (make it outside stream capture). Every call on a device
+ * shares its one array: calls whose work overlaps on one device (other
+ * threads, other streams without ordering) race and give wrong labels.
+ * Device-side failures are not reported by the call.                        */
+#define SEEDS_NOALLOC_MAX_BYTES (64u << 20)
+
+seeds_status seeds_segment_noalloc(const uint8_t *rgb, int32_t H, int32_t W,
+                                   int64_t row_pitch_bytes, int32_t num_superpixels,
+                                   const seeds_params *p, int32_t *labels_out, void *hip_stream);
+
 /* ---- Measurement ----------------------------------------------------------
  * LDS-atomic throughput of the current device, the secondary roof of the
  * refinement kernels: 4096 workgroups of 256 lanes each add 1024 times to

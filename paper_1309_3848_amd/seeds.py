@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
             "seeds_set_tuning": ([P, ctypes.POINTER(seeds_tuning)], S),
             "seeds_autotune": ([P, I32, ctypes.POINTER(seeds_tuning),
                                 ctypes.POINTER(ctypes.c_float), P], S),
+            "seeds_segment_noalloc": ([P, I32, I32, I64, I32, ctypes.POINTER(seeds_params), P, P],
+                                      S),
             "seeds_boundary_units": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P],
                                      S),
             "seeds_snapshot_size": ([P, ctypes.POINTER(I64)], S),
@@ -438,6 +440,21 @@ def seeds_autotune(ctx, reps: int = 3, stream=None):
     _check(lib().seeds_autotune(ctx, reps, ctypes.byref(t), ms, _stream(stream)))
     return ({"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap},
             [ms[i] for i in range(4)])
+
+
+def seeds_segment_noalloc(rgb: torch.Tensor, num_superpixels: int, params: seeds_params,
+                          out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Allocation-free init + refine + labels of one image into out (H x W
+    int32 device tensor); all state lives in the library's fixed device
+    array, so calls on one device must not overlap."""
+    _check_rgb(rgb)
+    H, W, _ = rgb.shape
+    if (out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous()
+            or tuple(out.shape) != (H, W)):
+        raise ValueError("out must be a contiguous H x W int32 device tensor")
+    _check(lib().seeds_segment_noalloc(rgb.data_ptr(), H, W, rgb.stride(0), num_superpixels,
+                                       ctypes.byref(params), out.data_ptr(), _stream(stream)))
+    return out
 
 
 def seeds_lds_atomic_rate(stream=None) -> float:

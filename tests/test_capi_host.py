@@ -237,6 +237,22 @@ def test_tuning_argument_checks(S):
     assert L.seeds_autotune(None, 3, None, None, None) == S.SEEDS_E_INVAL
 
 
+def test_noalloc_argument_checks_before_device_work(S):
+    L = S.lib()
+    p = S.make_params(levels=4)
+    d = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert L.seeds_segment_noalloc(None, 16, 16, 48, 4, ctypes.byref(p), d, None) == S.SEEDS_E_INVAL
+    assert L.seeds_segment_noalloc(d, 16, 16, 48, 4, ctypes.byref(p), None, None) == S.SEEDS_E_INVAL
+    assert L.seeds_segment_noalloc(d, 16, 16, 47, 4, ctypes.byref(p), d, None) == S.SEEDS_E_INVAL
+    assert "pitch" in S.seeds_last_error()
+    assert L.seeds_segment_noalloc(d, 16, 16, 48, 4, None, d, None) == S.SEEDS_E_INVAL
+    assert L.seeds_segment_noalloc(d, 0, 16, 48, 4, ctypes.byref(p), d, None) == S.SEEDS_E_INVAL
+    # a 4K frame's state (about 100 MB) exceeds the fixed array
+    assert L.seeds_segment_noalloc(d, 2160, 3840, 3 * 3840, 5000, ctypes.byref(p), d,
+                                   None) == S.SEEDS_E_INVAL
+    assert "allocation-free" in S.seeds_last_error()
+
+
 def test_fault_injection_argument_checks(S):
     L = S.lib()
     assert L.seeds_debug_inject_fault(2, 0) == S.SEEDS_E_INVAL
