@@ -75,19 +75,20 @@ def class_units(uw: int, uh: int, cls: int) -> int:
     return cw * ch
 
 
-def structural_phase_bytes(h: int, w: int, level: int, cls: int) -> float:
+def structural_phase_bytes(h: int, w: int, level: int, cls: int, lab_bytes: float = 4.0) -> float:
     """What one phase launch reads by construction: the whole unit-label plane
     of its level and the bins of its class's units."""
     uw, uh = units_of(h, w, level)
-    return 4.0 * uw * uh + 1.0 * class_units(uw, uh, cls) * (1 << level) ** 2
+    return lab_bytes * uw * uh + 1.0 * class_units(uw, uh, cls) * (1 << level) ** 2
 
 
-def fixed_bytes(h: int, w: int, levels: int):
+def fixed_bytes(h: int, w: int, levels: int, lab_bytes: float = 2.0):
     """(init, materialised pixel labels, output) bytes of one image: RGB read +
-    bins write + top-block labels; 4 B per pixel; 4 B per pixel."""
+    bins write + top-block labels; the pixel-label plane written once (2 B per
+    pixel in 16 bits); 4 B per pixel of int32 output."""
     n = h * w
     tw, th = units_of(h, w, levels - 1)
-    return 3.0 * n + 1.0 * n + 4.0 * tw * th, (4.0 * n if levels > 1 else 0.0), 4.0 * n
+    return (3.0 * n + 1.0 * n + 4.0 * tw * th, (lab_bytes * n if levels > 1 else 0.0), 4.0 * n)
 
 
 def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False, stream=None):
@@ -102,6 +103,9 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
     import torch
     n = len(dims)
     dev = torch.device("cuda:0")
+    # pixel labels are stored in 16 bits up to 65535 superpixels (the library's
+    # choice for the whole context); block grids in 32
+    lab16 = all(S.seeds_batch_num_superpixels(ctx, i) <= 65535 for i in range(n))
     labs = [torch.empty((h, w), dtype=torch.int32, device=dev) for h, w, _ in dims] if moves else None
     before = None
     total, struct, launches = 0.0, 0.0, 0
@@ -129,8 +133,9 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
                         S.seeds_batch_labels(ctx, i, labs[i], stream)
                         mv = float((labs[i] != before[q]).sum().item()) / (side * side)
                         rec["moved_units"] += mv
-                    total += 4.0 * uw * uh / 9.0 + b[i][1] + 4.0 * mv
-                    struct += structural_phase_bytes(h, w, lvl, cls)
+                    lb = 2.0 if (lvl == 0 and lab16) else 4.0
+                    total += lb * uw * uh / 9.0 + b[i][1] + lb * mv
+                    struct += structural_phase_bytes(h, w, lvl, cls, lb)
                     rec["boundary_pixels"] += b[i][1]
         rec["pixels"] = sum(dims[i][0] * dims[i][1] for i in part)
         # boundary fraction per sweep: pixels of boundary units over all pixels
@@ -143,10 +148,15 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
         per_level.append(rec)
     torch.cuda.synchronize()
     return {"launches": launches, "bytes": total, "bytes_per_launch": total / max(1, launches),
-            "structural_bytes_per_launch": struct / max(1, launches), "levels": per_level}
+            "structural_bytes_per_launch": struct / max(1, launches), "levels": per_level,
+            "pixel_label_bytes": 2 if lab16 else 4}
 
 
 def roofline(kernel, prof, avg_launch_us, traffic=None):
+    if prof is None:   # --skip-byte-pass (profiler runs): no boundary counts
+        return {"bound": "hbm", "kernel": kernel, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": traffic,
+                "avg_launch_us": round(avg_launch_us, 3), "note": "byte pass skipped"}
     achieved = prof["bytes_per_launch"] / (avg_launch_us * 1e-6) / 1e9
     st_achieved = prof["structural_bytes_per_launch"] / (avg_launch_us * 1e-6) / 1e9
     r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
@@ -278,10 +288,10 @@ def run_single(args, img, k, levels, name, steps, warmup, traffic_file=None, lds
     stream = torch.cuda.current_stream()
     ctx = S.seeds_init(rgb, k, params, stream)
     keff = S.seeds_num_superpixels(ctx)
-    tuning = None
-    if not args.no_autotune:
+    tuning = apply_tuning(S, ctx, args)
+    if tuning is None and not args.no_autotune:
         chosen, ms = S.seeds_autotune(ctx, 5, stream)
-        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 4) for m in ms]}
+        tuning = {"chosen": chosen, "ms_per_variant": [round(m, 4) for m in ms]}
 
     def step():
         S.seeds_reinit(ctx, rgb, stream)
@@ -318,14 +328,23 @@ def run_single(args, img, k, levels, name, steps, warmup, traffic_file=None, lds
     refine_ms = sum(a.elapsed_time(b) for a, b in zip(r0, r1)) / reps
     gpu_labels = out.cpu().numpy()
     # untimed pass: boundary units, moves and energies of every phase
-    S.seeds_reinit(ctx, rgb, stream)
-    prof = schedule_profile(S, ctx, [(h, w, levels)], list(range(levels - 1, -1, -1)), ITERS,
-                            moves=True, energy=True, stream=stream)
+    prof = None
+    if not args.skip_byte_pass:
+        S.seeds_reinit(ctx, rgb, stream)
+        prof = schedule_profile(S, ctx, [(h, w, levels)], list(range(levels - 1, -1, -1)), ITERS,
+                                moves=True, energy=True, stream=stream)
+    if args.copy_calibration:
+        # a known amount of traffic for scaling profiler byte counters
+        src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     S.seeds_destroy(ctx)
-    launches = prof["launches"]
+    launches = levels * ITERS * 9
     avg_us = refine_ms * 1e3 / launches
     init_b, mat_b, out_b = fixed_bytes(h, w, levels)
-    step_bytes = init_b + prof["bytes"] + mat_b + out_b
+    step_bytes = init_b + (prof["bytes"] if prof else 0.0) + mat_b + out_b
     traffic = measured_traffic(traffic_file) if traffic_file else None
     result = {
         "metric": METRIC, "value": round(h * w * steps / wall / 1e6, 2), "unit": "Mpixel/s",
@@ -337,9 +356,10 @@ def run_single(args, img, k, levels, name, steps, warmup, traffic_file=None, lds
                    "step": "reinit + refine + labels (device)"},
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4), "tuning": tuning,
         "refine_ms": round(refine_ms, 4), "launches_per_image": launches,
-        "algorithmic_bytes_per_step": int(step_bytes),
-        "algorithmic_bytes_per_pixel": round(step_bytes / (h * w), 2),
-        "hbm_frac_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 6),
+        "algorithmic_bytes_per_step": int(step_bytes) if prof else None,
+        "algorithmic_bytes_per_pixel": round(step_bytes / (h * w), 2) if prof else None,
+        "hbm_frac_step": (round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)
+                          if prof else None),
         "roofline": roofline("k_phase (one phase of the schedule per launch; block-level and "
                              "pixel-level variants)", prof, avg_us, traffic),
     }
@@ -356,6 +376,15 @@ def run_single(args, img, k, levels, name, steps, warmup, traffic_file=None, lds
         result["cpu_baseline"] = cb
         result["bitexact_vs_oracle"] = same
     return result
+
+
+def apply_tuning(S, ctx, args):
+    """--tuning c,r,items,rows: set that mapping (no autotuning)."""
+    if not args.tuning:
+        return None
+    c, r, it, rows = (int(v) for v in args.tuning.split(","))
+    S.seeds_set_tuning(ctx, c, r, it, rows)
+    return {"chosen": S.seeds_get_tuning(ctx), "set": True}
 
 
 def lds_peak(S, result, stream):
@@ -393,10 +422,10 @@ def run_batch(args) -> dict:
     stream = torch.cuda.current_stream()
     params = S.make_params(max(Ls), BINS, ITERS, GAMMA, RULE)
     ctx = S.seeds_batch_init(rgbs, Ks, params, levels=Ls, stream=stream)
-    tuning = None
-    if not args.no_autotune:
+    tuning = apply_tuning(S, ctx, args)
+    if tuning is None and not args.no_autotune:
         chosen, ms = S.seeds_autotune(ctx, 3, stream)
-        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 3) for m in ms]}
+        tuning = {"chosen": chosen, "ms_per_variant": [round(m, 4) for m in ms]}
 
     def step():
         S.seeds_batch_reinit(ctx, rgbs, stream)
@@ -432,9 +461,12 @@ def run_batch(args) -> dict:
     torch.cuda.synchronize()
     refine_ms = sum(a.elapsed_time(b) for a, b in zip(r0, r1)) / reps
     gpu_labels = [o.cpu().numpy() for o in outs]
-    S.seeds_batch_reinit(ctx, rgbs, stream)
     dims = [(s["H"], s["W"], s["levels"]) for s in specs]
-    prof = schedule_profile(S, ctx, dims, list(range(max(Ls) - 1, -1, -1)), ITERS, stream=stream)
+    prof = None
+    if not args.skip_byte_pass:
+        S.seeds_batch_reinit(ctx, rgbs, stream)
+        prof = schedule_profile(S, ctx, dims, list(range(max(Ls) - 1, -1, -1)), ITERS,
+                                stream=stream)
     S.seeds_sync(ctx, stream)
     S.seeds_destroy(ctx)
 
@@ -461,10 +493,10 @@ def run_batch(args) -> dict:
     for c in solo:
         S.seeds_destroy(c)
 
-    launches = prof["launches"]
+    launches = max(Ls) * ITERS * 9
     avg_us = refine_ms * 1e3 / launches
     fixed = [fixed_bytes(s["H"], s["W"], s["levels"]) for s in specs]
-    step_bytes = sum(sum(f) for f in fixed) + prof["bytes"]
+    step_bytes = sum(sum(f) for f in fixed) + (prof["bytes"] if prof else 0.0)
     solo_mpx = npx / (solo_ms * 1e-3) / 1e6
     value = npx * steps / wall / 1e6
     result = {
@@ -479,10 +511,12 @@ def run_batch(args) -> dict:
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
         "images_per_s": round(len(specs) * steps / wall, 1), "tuning": tuning,
         "refine_ms": round(refine_ms, 4), "launches_per_batch": launches,
-        "hbm_frac_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 6),
+        "hbm_frac_step": (round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)
+                          if prof else None),
         "plain_path": {"ms_per_batch": round(solo_ms, 4), "value": round(solo_mpx, 2),
                        "unit": "Mpixel/s", "labels_equal_to_batch": solo_same,
-                       "hbm_frac_step": round(step_bytes / (solo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6),
+                       "hbm_frac_step": (round(step_bytes / (solo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                               6) if prof else None),
                        "speedup_of_batch": round(value / solo_mpx, 2)},
         "roofline": roofline("k_phase (batch variant; one phase of every image per launch)",
                              prof, avg_us, None),
@@ -558,10 +592,10 @@ def run_stream(args) -> dict:
 
     ctx = S.seeds_init(frames[0], SK, params, stream)
     keff = S.seeds_num_superpixels(ctx)
-    tuning = None
-    if not args.no_autotune:
+    tuning = apply_tuning(S, ctx, args)
+    if tuning is None and not args.no_autotune:
         chosen, ms = S.seeds_autotune(ctx, 3, stream)
-        tuning = {"chosen": chosen, "refine_ms_per_variant": [round(m, 3) for m in ms]}
+        tuning = {"chosen": chosen, "ms_per_variant": [round(m, 4) for m in ms]}
     for f in range(min(warmup, nfr)):
         (cold if f == 0 else warm)(ctx, f)
     torch.cuda.synchronize()
@@ -591,8 +625,11 @@ def run_stream(args) -> dict:
     torch.cuda.synchronize()
     refine_ms = sum(a.elapsed_time(b) for a, b in r) / reps
     # boundary units of the pixel phases of a warm frame (untimed)
-    S.seeds_warm_start(ctx, frames[min(5, nfr - 1)], stream)
-    prof = schedule_profile(S, ctx, [(SH, SW, LEVELS)], [0], ITERS, moves=True, stream=stream)
+    prof = None
+    if not args.skip_byte_pass:
+        S.seeds_warm_start(ctx, frames[min(5, nfr - 1)], stream)
+        prof = schedule_profile(S, ctx, [(SH, SW, LEVELS)], [0], ITERS, moves=True,
+                                stream=stream)
     # the same frames each refined from scratch (the whole hierarchy)
     cold_reps = min(20, nfr)
     c = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -607,7 +644,7 @@ def run_stream(args) -> dict:
     S.seeds_destroy(ctx)
     labels_kept = {f: t.cpu().numpy() for f, t in labels_kept.items()}
 
-    avg_us = refine_ms * 1e3 / prof["launches"]
+    avg_us = refine_ms * 1e3 / (ITERS * 9)
     npx = SH * SW
     result = {
         "metric": METRIC, "value": round(npx * nfr / wall / 1e6, 2), "unit": "Mpixel/s",
@@ -1012,7 +1049,16 @@ def main() -> int:
                     help="keep the default launch mapping instead of timing the four settings "
                          "(seeds_autotune) before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tuning", default=None,
+                    help="pixel_compaction,xcd_remap,items_per_group,init_rows to set instead of "
+                         "autotuning (for profiler runs of the tuned mapping)")
     ap.add_argument("--skip", default="", help="comma-separated nested workloads to leave out")
+    ap.add_argument("--skip-byte-pass", action="store_true",
+                    help="leave out the untimed phase-by-phase pass that counts boundary units "
+                         "(for profiler runs: its hook kernels would mix into the statistics)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="single image: also run one 64 MiB device-to-device copy (a known "
+                         "amount of HBM traffic for scaling profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -200,8 +200,8 @@ typedef enum {
 seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
 
 /* ---- Tuning ---------------------------------------------------------------
- * How the per-phase launches map work to workgroups. The choice never changes
- * a result: labels, histograms and sizes are the same for every setting.
+ * How the launches map work to workgroups. The choice never changes a
+ * result: labels, histograms and sizes are the same for every setting.
  *   pixel_compaction  1: pixel phases first test every pixel of the class
  *                     cheaply and pack the movable ones into dense wavefronts
  *                     for the full decision; 0: every thread decides its own
@@ -210,22 +210,38 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  *   xcd_remap         1: workgroups are numbered so that each of the eight
  *                     XCDs works a contiguous band of the image (fewer L2
  *                     misses); 0: hardware order.
- * Default: pixel_compaction 0, xcd_remap 1.                                  */
+ *   items_per_group   1, 2 or 4: work items (a 64 x 4 tile of class pixels,
+ *                     or one round of class blocks) each workgroup of a
+ *                     phase launch takes; more items mean fewer, longer
+ *                     workgroups.
+ *   init_rows         8, 16 or 32: rows of the 64-column tiles of the
+ *                     initialisation and warm-start kernels (2, 4 or 8
+ *                     pixels per thread).
+ * Default: pixel_compaction 0, xcd_remap 1, items_per_group 1, init_rows 16. */
 typedef struct {
     int32_t pixel_compaction;
     int32_t xcd_remap;
+    int32_t items_per_group;
+    int32_t init_rows;
 } seeds_tuning;
 
 seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out);
 seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t);
 
-/* Time a whole refinement (reps runs after one warm-up, median) for each of
- * the four settings on this context's own images and keep the fastest. The
- * context is re-initialised from its images before every run and once more
- * at the end, so it returns freshly initialised (as after seeds_reinit); the
- * call waits for the stream. *chosen and ms_per_variant[4] (either may be
- * NULL) receive the choice and the medians, variant v = 2 (1 - xcd_remap) +
- * (1 - pixel_compaction). Not for SEEDS_LAUNCH_PERSISTENT; reps in [1,50].  */
+/* Autotuner. First the phase mapping: every combination of pixel_compaction,
+ * xcd_remap and items_per_group (12 variants) is timed on whole refinements
+ * of the context's own images (reps runs after one warm-up that captures the
+ * graph; median) and the fastest kept. Then init_rows (3 variants), timed on
+ * initialisations with that mapping. The context is re-initialised before
+ * every run and once more at the end, so it returns freshly initialised (as
+ * after seeds_reinit); the call waits for the stream. *chosen and
+ * ms_per_variant[SEEDS_TUNE_VARIANTS] (either may be NULL) receive the
+ * choice and the medians: entry v < 12 is the mapping with items_per_group
+ * = 1, 2, 4 for v / 4 = 0, 1, 2 and, within, v % 4 = 2 (1 - xcd_remap) +
+ * (1 - pixel_compaction); entry 12 + r the initialisation with init_rows =
+ * 8, 16, 32 for r = 0, 1, 2. Not for SEEDS_LAUNCH_PERSISTENT; reps in
+ * [1,50].                                                                    */
+#define SEEDS_TUNE_VARIANTS 15
 seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
                             float *ms_per_variant, void *hip_stream);
 

@@ -93,10 +93,13 @@ struct seeds_ctx {
     int64_t *d_pitch = nullptr;       // batch: device table of row pitches
     std::vector<const uint8_t *> rgb;  // host copies of the two tables
     std::vector<int64_t> pitch;
-    std::vector<LaunchMap> phase_map;    // batch: [level * 9 + cls]
-    std::vector<LaunchMap> descend_map;  // batch: [level]
-    LaunchMap init_map;                  // batch
-    int log_groups = 1, log_cap = 1;  // move-log shape of the per-phase launches
+    // batch maps, one set per tuning choice of items per workgroup / init rows
+    std::vector<LaunchMap> phase_map[3];  // batch: [item choice][level * 9 + cls]
+    std::vector<LaunchMap> descend_map;   // batch: [level]
+    LaunchMap init_map[3];                // batch: [row choice]
+    // move-log shape of the per-phase launches for each items-per-workgroup
+    // choice (the slab holds the largest)
+    int log_groups_of[3] = {1, 1, 1}, log_cap_of[3] = {1, 1, 1};
     PersistentGeom geom{};            // single image only
     int mode = SEEDS_LAUNCH_GRAPH;    // seeds_launch_mode
     PhaseTuning tune;                 // mapping of the per-phase launches
@@ -189,22 +192,21 @@ BatchArgs batch_args(const seeds_ctx *ctx) {
     b.imgs = ctx->d_imgs;
     b.nimg = ctx->nimg;
     b.ar = ctx->ar;
-    b.log_cap = ctx->log_cap;
-    b.log_groups = ctx->log_groups;
+    const int it = item_index(ctx->tune.items);
+    b.log_cap = ctx->log_cap_of[it];
+    b.log_groups = ctx->log_groups_of[it];
+    b.items = ctx->tune.items;
     return b;
 }
 
-LaunchMap phase_launch(const seeds_ctx *ctx, int level, int cls) {
-    if (ctx->nimg == 1) return {nullptr, phase_groups(ctx->imgs[0].d, level, cls)};
-    return ctx->phase_map[level * 9 + cls];
-}
+
 LaunchMap descend_launch(const seeds_ctx *ctx, int level) {
     if (ctx->nimg == 1) return {nullptr, descend_groups(ctx->imgs[0].d, level)};
     return ctx->descend_map[level];
 }
 LaunchMap init_launch(const seeds_ctx *ctx) {
-    if (ctx->nimg == 1) return {nullptr, init_groups(ctx->imgs[0].d)};
-    return ctx->init_map;
+    if (ctx->nimg == 1) return {nullptr, init_groups(ctx->imgs[0].d, ctx->tune.init_rows)};
+    return ctx->init_map[row_index(ctx->tune.init_rows)];
 }
 
 // Level of image i's labels, and the unit grid holding them.
@@ -225,7 +227,7 @@ seeds_status start_schedule(seeds_ctx *ctx, hipStream_t s) {
                        : launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
     if (e == hipSuccess)
         e = launch_init(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
-                        ctx->d_rgb, ctx->d_pitch, m.groups, s);
+                        ctx->d_rgb, ctx->d_pitch, m.groups, ctx->tune.init_rows, s);
     if (e != hipSuccess) return device_error(ctx, e, "init launch");
     ctx->sched.level = ctx->top.L - 1;
     ctx->sched.cur_level = ctx->top.L - 1;
@@ -266,8 +268,9 @@ hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_pha
             if (m.groups > 0) e = launch_descend(b, one, m.map, sched.level, m.groups, s);
         } else {
             const int level = sched.level;
-            const LaunchMap m = a.phase_map ? a.phase_map[level * 9 + cls]
-                                            : LaunchMap{nullptr, phase_groups(one.d, level, cls)};
+            const LaunchMap m =
+                a.phase_map ? a.phase_map[level * 9 + cls]
+                            : LaunchMap{nullptr, phase_launch_groups(one.d, level, cls, a.tune.items)};
             ++stamp;
             if (m.groups == 0) {
                 // no unit of this class in any image: nothing moves; the
@@ -308,7 +311,7 @@ seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_ou
     a.b = batch_args(ctx);
     a.one = ctx->imgs[0];
     a.top = ctx->top;
-    a.phase_map = ctx->nimg > 1 ? ctx->phase_map.data() : nullptr;
+    a.phase_map = ctx->nimg > 1 ? ctx->phase_map[item_index(ctx->tune.items)].data() : nullptr;
     a.descend_map = ctx->nimg > 1 ? ctx->descend_map.data() : nullptr;
     a.src_elems = ctx->src_elems;
     a.tune = ctx->tune;
@@ -511,35 +514,49 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     ctx->src_elems = (int64_t)src;
     // workgroup maps of a batch
     std::vector<int2> maps;
-    std::vector<std::pair<size_t, int>> phase_pos(Lmax * 9), descend_pos(Lmax);
-    std::pair<size_t, int> init_pos{0, 0};
+    std::vector<std::pair<size_t, int>> phase_pos[3], descend_pos(Lmax);
+    std::pair<size_t, int> init_pos[3];
     if (ctx->nimg > 1) {
-        for (int l = 0; l < Lmax; ++l)
-            for (int c = 0; c < 9; ++c)
-                phase_pos[l * 9 + c] = append_map(
-                    maps, ctx->imgs, l, [&](const Dims &d) { return phase_groups(d, l, c); });
+        for (int v = 0; v < 3; ++v) {
+            phase_pos[v].resize(Lmax * 9);
+            for (int l = 0; l < Lmax; ++l)
+                for (int c = 0; c < 9; ++c)
+                    phase_pos[v][l * 9 + c] = append_map(maps, ctx->imgs, l, [&](const Dims &d) {
+                        return phase_launch_groups(d, l, c, kItemChoices[v]);
+                    });
+        }
         for (int l = 1; l < Lmax; ++l)
             descend_pos[l] =
                 append_map(maps, ctx->imgs, l, [&](const Dims &d) { return descend_groups(d, l); });
-        init_pos = append_map(maps, ctx->imgs, 0, [](const Dims &d) { return init_groups(d); });
+        for (int v = 0; v < 3; ++v)
+            init_pos[v] = append_map(maps, ctx->imgs, 0,
+                                     [&](const Dims &d) { return init_groups(d, kRowChoices[v]); });
     }
     // move-log shape: as many slots as the largest phase launch, each as long
     // as the most deltas one workgroup of any image can produce in a phase
-    ctx->log_groups = 1;
-    ctx->log_cap = 1;
-    for (int l = 0; l < Lmax; ++l)
-        for (int c = 0; c < 9; ++c) {
-            int n = 0;
-            for (const auto &g : ctx->imgs)
-                if (g.d.L - 1 >= l) n += phase_groups(g.d, l, c);
-            ctx->log_groups = std::max(ctx->log_groups, n);
-        }
+    // (per choice of work items per workgroup: a workgroup's log holds the
+    // deltas of all its items)
+    int round_cap = 1;
     for (const auto &g : ctx->imgs)
-        for (int l = 0; l < g.d.L; ++l) ctx->log_cap = std::max(ctx->log_cap, deltas_per_round(g.d, l));
+        for (int l = 0; l < g.d.L; ++l) round_cap = std::max(round_cap, deltas_per_round(g.d, l));
+    size_t log_entries = 0, log_slots = 0;
+    for (int v = 0; v < 3; ++v) {
+        int groups = 1;
+        for (int l = 0; l < Lmax; ++l)
+            for (int c = 0; c < 9; ++c) {
+                int n = 0;
+                for (const auto &g : ctx->imgs)
+                    if (g.d.L - 1 >= l) n += phase_launch_groups(g.d, l, c, kItemChoices[v]);
+                groups = std::max(groups, n);
+            }
+        ctx->log_groups_of[v] = groups;
+        ctx->log_cap_of[v] = round_cap * kItemChoices[v];
+        log_entries = std::max(log_entries, (size_t)groups * ctx->log_cap_of[v]);
+        log_slots = std::max(log_slots, (size_t)groups);
+    }
     if (ctx->nimg == 1) ctx->geom = persistent_geometry(in[0].d, ctx->device, 2);
-    const size_t log_entries = std::max((size_t)ctx->geom.groups * ctx->geom.log_cap,
-                                        (size_t)ctx->log_groups * ctx->log_cap);
-    const size_t log_slots = (size_t)std::max(ctx->geom.groups, ctx->log_groups);
+    log_entries = std::max(log_entries, (size_t)ctx->geom.groups * ctx->geom.log_cap);
+    log_slots = std::max(log_slots, (size_t)ctx->geom.groups);
     // one slab
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -590,13 +607,15 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     ctx->d_pitch = (int64_t *)(base + o_pitch);
     const int2 *d_maps = (const int2 *)(base + o_maps);
     if (ctx->nimg > 1) {
-        ctx->phase_map.resize(Lmax * 9);
+        for (int v = 0; v < 3; ++v) {
+            ctx->phase_map[v].resize(Lmax * 9);
+            for (int i = 0; i < Lmax * 9; ++i)
+                ctx->phase_map[v][i] = {d_maps + phase_pos[v][i].first, phase_pos[v][i].second};
+            ctx->init_map[v] = {d_maps + init_pos[v].first, init_pos[v].second};
+        }
         ctx->descend_map.resize(Lmax);
-        for (int i = 0; i < Lmax * 9; ++i)
-            ctx->phase_map[i] = {d_maps + phase_pos[i].first, phase_pos[i].second};
         for (int l = 1; l < Lmax; ++l)
             ctx->descend_map[l] = {d_maps + descend_pos[l].first, descend_pos[l].second};
-        ctx->init_map = {d_maps + init_pos.first, init_pos.second};
     }
     // tables, in stream order; `maps` is local, so wait for the copies
     e = hipMemcpyAsync(ctx->d_imgs, ctx->imgs.data(), ctx->imgs.size() * sizeof(ImageDesc),
@@ -805,7 +824,7 @@ seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t
                        : launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
     if (e == hipSuccess)
         e = launch_rehist(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
-                          ctx->d_rgb, ctx->d_pitch, m.groups, s);
+                          ctx->d_rgb, ctx->d_pitch, m.groups, ctx->tune.init_rows, s);
     if (e != hipSuccess) return device_error(ctx, e, "warm start launch");
     ctx->sched.cur_level = -1;
     ctx->sched.cur_sweep = 0;
@@ -1232,6 +1251,8 @@ seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out) {
     if (!ctx || !out) return fail(SEEDS_E_INVAL, "NULL argument");
     out->pixel_compaction = ctx->tune.pixel_compact ? 1 : 0;
     out->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
+    out->items_per_group = ctx->tune.items;
+    out->init_rows = ctx->tune.init_rows;
     return SEEDS_OK;
 }
 
@@ -1239,12 +1260,55 @@ seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t) {
     if (!ctx || !t) return fail(SEEDS_E_INVAL, "NULL argument");
     if ((t->pixel_compaction != 0 && t->pixel_compaction != 1) ||
         (t->xcd_remap != 0 && t->xcd_remap != 1))
-        return fail(SEEDS_E_INVAL, "tuning fields are 0 or 1");
+        return fail(SEEDS_E_INVAL, "pixel_compaction and xcd_remap are 0 or 1");
+    if (t->items_per_group != 1 && t->items_per_group != 2 && t->items_per_group != 4)
+        return fail(SEEDS_E_INVAL, "items_per_group %d is not 1, 2 or 4", t->items_per_group);
+    if (t->init_rows != 8 && t->init_rows != 16 && t->init_rows != 32)
+        return fail(SEEDS_E_INVAL, "init_rows %d is not 8, 16 or 32", t->init_rows);
     ctx->tune.pixel_compact = t->pixel_compaction != 0;
     ctx->tune.xcd_remap = t->xcd_remap != 0;
+    ctx->tune.items = t->items_per_group;
+    ctx->tune.init_rows = t->init_rows;
     clear_graphs(ctx);
     return SEEDS_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Median over reps timed runs (after one untimed warm-up, which also captures
+// the refinement graph) of a fresh initialisation (refine = false) or of the
+// whole refinement that follows one (refine = true).
+seeds_status time_runs(seeds_ctx *ctx, int reps, bool refine, hipEvent_t e0, hipEvent_t e1,
+                       hipStream_t s, float *median) {
+    std::vector<float> t;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r <= reps; ++r) {
+        if (refine) {
+            seeds_status st = start_schedule(ctx, s);
+            if (st != SEEDS_OK) return st;
+        }
+        e = hipEventRecord(e0, s);
+        if (e != hipSuccess) break;
+        seeds_status st = refine ? run_schedule(ctx, -1, nullptr, s) : start_schedule(ctx, s);
+        if (st != SEEDS_OK) return st;
+        e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (r > 0) t.push_back(ms);
+    }
+    if (e != hipSuccess) return device_error(ctx, e, "autotune timing");
+    std::sort(t.begin(), t.end());
+    *median = t[t.size() / 2];
+    return SEEDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
                             float *ms_per_variant, void *hip_stream) {
@@ -1257,46 +1321,52 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return device_error(ctx, e, "hipEventCreate");
+    }
+    // the phase mapping (compaction x remap x items per workgroup), timed on
+    // whole refinements; then the rows of the initialisation tiles, timed on
+    // initialisations with the chosen mapping
     float best_ms = 0;
     int best = 0;
-    for (int v = 0; v < 4 && e == hipSuccess; ++v) {
+    for (int v = 0; v < 12 && st == SEEDS_OK; ++v) {
         ctx->tune.pixel_compact = (v & 1) == 0;
         ctx->tune.xcd_remap = (v & 2) == 0;
+        ctx->tune.items = kItemChoices[v / 4];
         clear_graphs(ctx);
-        std::vector<float> t;
-        for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r = 0 warms up (capture)
-            st = start_schedule(ctx, s);
-            if (st != SEEDS_OK) break;
-            e = hipEventRecord(e0, s);
-            if (e != hipSuccess) break;
-            st = run_schedule(ctx, -1, nullptr, s);
-            if (st != SEEDS_OK) break;
-            e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (r > 0) t.push_back(ms);
-        }
-        if (st != SEEDS_OK || e != hipSuccess) break;
-        std::sort(t.begin(), t.end());
-        const float med = t[t.size() / 2];
+        float med = 0;
+        st = time_runs(ctx, reps, true, e0, e1, s, &med);
+        if (st != SEEDS_OK) break;
         if (ms_per_variant) ms_per_variant[v] = med;
         if (v == 0 || med < best_ms) {
             best_ms = med;
             best = v;
         }
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (st != SEEDS_OK) return st;
-    if (e != hipSuccess) return device_error(ctx, e, "autotune timing");
-    ctx->tune.pixel_compact = (best & 1) == 0;
-    ctx->tune.xcd_remap = (best & 2) == 0;
-    clear_graphs(ctx);
-    if (chosen) {
-        chosen->pixel_compaction = ctx->tune.pixel_compact ? 1 : 0;
-        chosen->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
+    if (st == SEEDS_OK) {
+        ctx->tune.pixel_compact = (best & 1) == 0;
+        ctx->tune.xcd_remap = (best & 2) == 0;
+        ctx->tune.items = kItemChoices[best / 4];
+        clear_graphs(ctx);
     }
+    int best_rows = 1;
+    for (int v = 0; v < 3 && st == SEEDS_OK; ++v) {
+        ctx->tune.init_rows = kRowChoices[v];
+        float med = 0;
+        st = time_runs(ctx, reps, false, e0, e1, s, &med);
+        if (st != SEEDS_OK) break;
+        if (ms_per_variant) ms_per_variant[12 + v] = med;
+        if (v == 0 || med < best_ms) {
+            best_ms = med;
+            best_rows = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SEEDS_OK) return st;
+    ctx->tune.init_rows = kRowChoices[best_rows];
+    if (chosen) (void)seeds_get_tuning(ctx, chosen);
     return start_schedule(ctx, s);
 }
 

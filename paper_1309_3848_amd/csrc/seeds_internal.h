@@ -166,6 +166,7 @@ struct BatchArgs {
     Arenas ar;
     int log_cap;
     int log_groups;
+    int items = 1;  // phase work items per workgroup (batch maps count workgroups with it)
 };
 
 constexpr int kPersistentThreads = 256;
@@ -212,6 +213,12 @@ __host__ __device__ inline int phase_groups(const Dims &d, int level, int cls) {
     return (class_units(d, level, cls) + per - 1) / per;
 }
 
+// Workgroups of one image in a phase launch that gives each workgroup `items`
+// work items (the last one may get fewer).
+__host__ __device__ inline int phase_launch_groups(const Dims &d, int level, int cls, int items) {
+    return (phase_groups(d, level, cls) + items - 1) / items;
+}
+
 // Upper bound on the log entries (deltas) one workgroup produces in one work
 // item of a phase at `level`.
 __host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
@@ -228,9 +235,11 @@ __host__ __device__ inline int descend_groups(const Dims &d, int level) {
     const int fw = units_w(d, level), fh = units_h(d, level);
     return fh * ((fw + kPersistentThreads - 1) / kPersistentThreads);
 }
-constexpr int kInitTW = 64, kInitTH = 16;
-__host__ __device__ inline int init_groups(const Dims &d) {
-    return ((d.W + kInitTW - 1) / kInitTW) * ((d.H + kInitTH - 1) / kInitTH);
+// Initialisation and warm-start tiles: kInitTW x rows pixels, rows in
+// {8, 16, 32} (a tuning choice; kInitTH by default).
+constexpr int kInitTW = 64, kInitTH = 16, kMaxInitTH = 32;
+__host__ __device__ inline int init_groups(const Dims &d, int rows = kInitTH) {
+    return ((d.W + kInitTW - 1) / kInitTW) * ((d.H + rows - 1) / rows);
 }
 
 // Persistent-kernel launch geometry, fixed per single-image context.
@@ -258,7 +267,7 @@ hipError_t launch_narrow_labels(const Arenas &a, int64_t at, const int32_t *src,
                                 hipStream_t s);
 hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                        int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
-                       const int64_t *pitch_table, int groups, hipStream_t s);
+                       const int64_t *pitch_table, int groups, int rows, hipStream_t s);
 // One phase as one launch. pass: 0 decide and apply, 1 exact-rule decide
 // only, 2 exact-rule apply. replay_groups: workgroups of the previous phase
 // launch, whose logs (parity par ^ 1) this launch adds to its write copy.
@@ -267,7 +276,13 @@ hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *
 struct PhaseTuning {
     bool pixel_compact = false;  // pixel phases: pre-test and compaction
     bool xcd_remap = true;      // workgroups numbered in contiguous bands per XCD
+    int items = 1;              // work items (pixel tiles, block rounds) per workgroup: 1, 2, 4
+    int init_rows = kInitTH;    // rows of an initialisation / warm-start tile: 8, 16, 32
 };
+constexpr int kItemChoices[3] = {1, 2, 4};
+constexpr int kRowChoices[3] = {8, 16, 32};
+__host__ __device__ inline int item_index(int items) { return items == 4 ? 2 : items == 2 ? 1 : 0; }
+__host__ __device__ inline int row_index(int rows) { return rows == 32 ? 2 : rows == 8 ? 0 : 1; }
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
                         int replay_groups, const PhaseTuning &tune, hipStream_t s);
@@ -285,7 +300,7 @@ hipError_t launch_sizes(const Dims &d, int32_t *state0, int32_t *state1, hipStre
 // map and tables as launch_init.
 hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                          int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
-                         const int64_t *pitch_table, int groups, hipStream_t s);
+                         const int64_t *pitch_table, int groups, int rows, hipStream_t s);
 hipError_t launch_expand(const Dims &d, const int32_t *units, int level, int32_t *out,
                          hipStream_t s);
 

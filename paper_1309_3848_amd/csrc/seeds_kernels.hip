@@ -39,10 +39,12 @@ __device__ __forceinline__ int grid_row(int y, const Dims &d, int bh) {
 extern __shared__ int32_t dyn_hist[];
 struct InitSlots {
     int32_t size[kMaxSlots];
-    int32_t col[kInitTW], row[kInitTH];  // superpixel column / row of the tile's columns / rows
+    int32_t col[kInitTW], row[kMaxInitTH];  // superpixel column / row of the tile's columns / rows
 };
 
-// One tile of one image. st0 / st1: the image's state in both copies.
+// One tile of kInitTW x TH pixels of one image (TH / 4 pixels per thread).
+// st0 / st1: the image's state in both copies.
+template <int TH>
 __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
                           uint8_t *__restrict__ bins, int32_t *__restrict__ top,
                           uint16_t *__restrict__ top16, int32_t *__restrict__ st0,
@@ -50,8 +52,8 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     const int64_t khs = (int64_t)d.K * d.hs;
     const int bw = (d.W + d.T - 1) / d.T, bh = (d.H + d.T - 1) / d.T;
     const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
-    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * kInitTH;
-    const int x1 = min(x0 + kInitTW, d.W) - 1, y1 = min(y0 + kInitTH, d.H) - 1;
+    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * TH;
+    const int x1 = min(x0 + kInitTW, d.W) - 1, y1 = min(y0 + TH, d.H) - 1;
     const int sx_lo = grid_col(x0, d, bw), sx_hi = grid_col(x1, d, bw);
     const int sy_lo = grid_row(y0, d, bh), sy_hi = grid_row(y1, d, bh);
     const int nsx = sx_hi - sx_lo + 1;
@@ -59,7 +61,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     const bool local = nslots <= kMaxSlots;
     // every pixel's colour is loaded first, from addresses clamped into the
     // image (a load behind a branch is waited for at the end of the branch)
-    constexpr int kRows = kInitTH * kInitTW / kThreads;
+    constexpr int kRows = TH * kInitTW / kThreads;
     const int x = x0 + (int)(threadIdx.x % kInitTW), xc = min(x, d.W - 1);
     uint8_t c0[kRows], c1[kRows], c2[kRows];
 #pragma unroll
@@ -78,7 +80,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     // each instead of two 64-bit divisions per pixel
     if (threadIdx.x < kInitTW)
         sl.col[threadIdx.x] = grid_col(min(x0 + (int)threadIdx.x, d.W - 1), d, bw);
-    else if (threadIdx.x < kInitTW + kInitTH)
+    else if (threadIdx.x < kInitTW + TH)
         sl.row[threadIdx.x - kInitTW] = grid_row(min(y0 + (int)threadIdx.x - kInitTW, d.H - 1), d, bh);
     __syncthreads();
     const int sh = __builtin_ctz(d.T);  // T is a power of two
@@ -131,6 +133,7 @@ __device__ void init_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_
     }
 }
 
+template <int TH>
 __device__ __forceinline__ void init_image(const BatchArgs &b, const ImageDesc &g,
                                            const uint8_t *rgb, int64_t pitch, int tile,
                                            InitSlots &sl) {
@@ -139,10 +142,11 @@ __device__ __forceinline__ void init_image(const BatchArgs &b, const ImageDesc &
     // with one level the top blocks are the pixels (int32 or 16-bit plane)
     int32_t *top = d.L > 1 ? b.ar.bl + g.bl[(d.L - 1) & 1] : (b.ar.lab ? b.ar.lab + g.lab : nullptr);
     uint16_t *top16 = d.L == 1 && b.ar.lab16 ? b.ar.lab16 + g.lab : nullptr;
-    init_tile(d, rgb, pitch, b.ar.bins + g.bins, top, top16, b.ar.state[0] + g.state,
-              b.ar.state[1] + g.state, tile, sl);
+    init_tile<TH>(d, rgb, pitch, b.ar.bins + g.bins, top, top16, b.ar.state[0] + g.state,
+                  b.ar.state[1] + g.state, tile, sl);
 }
 
+template <int TH>
 __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
                                                    const uint8_t *rgb_one, int64_t pitch_one,
                                                    const int2 *map,
@@ -151,11 +155,11 @@ __global__ __launch_bounds__(kThreads) void k_init(BatchArgs b, ImageDesc one,
     __shared__ InitSlots sl;
     const int lg = xcd_group();
     if (b.nimg == 1) {
-        init_image(b, one, rgb_one, pitch_one, lg, sl);
+        init_image<TH>(b, one, rgb_one, pitch_one, lg, sl);
         return;
     }
     const int2 e = map[lg];
-    init_image(b, b.imgs[e.x], rgb_table[e.x], pitch_table[e.x], e.y, sl);
+    init_image<TH>(b, b.imgs[e.x], rgb_table[e.x], pitch_table[e.x], e.y, sl);
 }
 
 // Serving engine: items of newly admitted images. Their state regions are
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_init_mixed(BatchArgs b, TickList l
     __shared__ InitSlots sl;
     const int lg = xcd_group();
     const TickItem &it = l.items[find_tick_item(l, lg)];
-    init_image(b, it.g, it.rgb, it.pitch, lg - it.first, sl);
+    init_image<kInitTH>(b, it.g, it.rgb, it.pitch, lg - it.first, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,16 +216,15 @@ __device__ __forceinline__ int rehist_entry(RehistLds &r, int32_t k, bool insert
     return -1;
 }
 
-constexpr int kRehistPx = kInitTW * kInitTH / kThreads;  // pixels per thread
-
-template <typename LabT>
+template <typename LabT, int TH>
 __device__ void rehist_tile(const Dims &d, const uint8_t *__restrict__ rgb, int64_t pitch,
                             uint8_t *__restrict__ bins, const LabT *__restrict__ lab,
                             int32_t *__restrict__ st0, int32_t *__restrict__ st1, int tile,
                             RehistLds &r) {
+    constexpr int kRehistPx = kInitTW * TH / kThreads;  // pixels per thread
     const int64_t khs = (int64_t)d.K * d.hs;
     const int tiles_x = (d.W + kInitTW - 1) / kInitTW;
-    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * kInitTH;
+    const int x0 = (tile % tiles_x) * kInitTW, y0 = (tile / tiles_x) * TH;
     for (int i = threadIdx.x; i < kRehistKeys; i += kThreads) {
         r.key[i] = -1;
         r.slot[i] = -1;
@@ -344,7 +347,7 @@ __device__ __forceinline__ const int32_t *rehist_plane<int32_t>(const Arenas &a)
 template <>
 __device__ __forceinline__ const uint16_t *rehist_plane<uint16_t>(const Arenas &a) { return a.lab16; }
 
-template <typename LabT>
+template <typename LabT, int TH>
 __global__ __launch_bounds__(kThreads) void k_rehist(BatchArgs b, ImageDesc one,
                                                      const uint8_t *rgb_one, int64_t pitch_one,
                                                      const int2 *map,
@@ -354,14 +357,14 @@ __global__ __launch_bounds__(kThreads) void k_rehist(BatchArgs b, ImageDesc one,
     const int lg = xcd_group();
     const LabT *lab = rehist_plane<LabT>(b.ar);
     if (b.nimg == 1) {
-        rehist_tile(one.d, rgb_one, pitch_one, b.ar.bins, lab, b.ar.state[0], b.ar.state[1], lg,
-                    r);
+        rehist_tile<LabT, TH>(one.d, rgb_one, pitch_one, b.ar.bins, lab, b.ar.state[0],
+                              b.ar.state[1], lg, r);
         return;
     }
     const int2 e = map[lg];
     const ImageDesc g = b.imgs[e.x];
-    rehist_tile(g.d, rgb_table[e.x], pitch_table[e.x], b.ar.bins + g.bins, lab + g.lab,
-                b.ar.state[0] + g.state, b.ar.state[1] + g.state, e.y, r);
+    rehist_tile<LabT, TH>(g.d, rgb_table[e.x], pitch_table[e.x], b.ar.bins + g.bins, lab + g.lab,
+                          b.ar.state[0] + g.state, b.ar.state[1] + g.state, e.y, r);
 }
 
 // 16-bit pixel labels to int32 and back (readback, snapshots), over the
@@ -424,8 +427,9 @@ hipError_t launch_fill(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_init(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                        int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
-                       const int64_t *pitch_table, int groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(groups), dim3(kThreads), kMaxSlots * one.d.hs * 4, s, b, one,
+                       const int64_t *pitch_table, int groups, int rows, hipStream_t s) {
+    decltype(&k_init<kInitTH>) fn = rows == 8 ? k_init<8> : rows == 32 ? k_init<32> : k_init<16>;
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kThreads), kMaxSlots * one.d.hs * 4, s, b, one,
                        rgb_one, pitch_one, map, rgb_table, pitch_table);
     return hipGetLastError();
 }
@@ -442,15 +446,16 @@ hipError_t launch_init_mixed(const BatchArgs &b, const TickList &l, int groups, 
 
 hipError_t launch_rehist(const BatchArgs &b, const ImageDesc &one, const uint8_t *rgb_one,
                          int64_t pitch_one, const int2 *map, const uint8_t *const *rgb_table,
-                         const int64_t *pitch_table, int groups, hipStream_t s) {
+                         const int64_t *pitch_table, int groups, int rows, hipStream_t s) {
+    decltype(&k_rehist<int32_t, kInitTH>) fn;
     if (b.ar.lab16)
-        hipLaunchKernelGGL(k_rehist<uint16_t>, dim3(groups), dim3(kThreads),
-                           kRehistSlots * one.d.hs * 4, s, b, one, rgb_one, pitch_one, map,
-                           rgb_table, pitch_table);
+        fn = rows == 8 ? k_rehist<uint16_t, 8> : rows == 32 ? k_rehist<uint16_t, 32>
+                                                            : k_rehist<uint16_t, 16>;
     else
-        hipLaunchKernelGGL(k_rehist<int32_t>, dim3(groups), dim3(kThreads),
-                           kRehistSlots * one.d.hs * 4, s, b, one, rgb_one, pitch_one, map,
-                           rgb_table, pitch_table);
+        fn = rows == 8 ? k_rehist<int32_t, 8> : rows == 32 ? k_rehist<int32_t, 32>
+                                                           : k_rehist<int32_t, 16>;
+    hipLaunchKernelGGL(fn, dim3(groups), dim3(kThreads), kRehistSlots * one.d.hs * 4, s, b, one,
+                       rgb_one, pitch_one, map, rgb_table, pitch_table);
     return hipGetLastError();
 }
 

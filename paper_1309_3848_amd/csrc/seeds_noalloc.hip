@@ -148,7 +148,7 @@ extern "C" seeds_status seeds_segment_noalloc(const uint8_t *rgb, int32_t H, int
     if (e == hipSuccess) e = launch_fill(b.ar.state[0], 0, 2 * o.state_elems, s);
     if (e == hipSuccess)
         e = launch_init(b, a.one, rgb, row_pitch_bytes, nullptr, nullptr, nullptr,
-                        init_groups(d), s);
+                        init_groups(d), kInitTH, s);
     Sched sched;
     sched.level = sched.cur_level = d.L - 1;
     sched.cur_sweep = sched.cur_class = 0;

@@ -21,7 +21,7 @@ __device__ __forceinline__ ImageView resolve(const BatchArgs &b, const ImageDesc
     } else {
         const int2 e = map[lg];
         const ImageDesc g = b.imgs[e.x];
-        return make_view(b, g, e.y, phase_groups(g.d, level, cls));
+        return make_view(b, g, e.y, phase_launch_groups(g.d, level, cls, b.items));
     }
 }
 

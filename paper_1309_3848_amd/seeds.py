@@ -55,7 +55,11 @@ class seeds_server_stats(ctypes.Structure):
 
 
 class seeds_tuning(ctypes.Structure):
-    _fields_ = [("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+    _fields_ = [("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("items_per_group", ctypes.c_int32), ("init_rows", ctypes.c_int32)]
+
+
+SEEDS_TUNE_VARIANTS = 15
 
 
 class seeds_quality(ctypes.Structure):
@@ -421,25 +425,30 @@ def seeds_server_destroy(srv) -> None:
     _check(lib().seeds_server_destroy(srv))
 
 
+def _tuning_dict(t: seeds_tuning) -> dict:
+    return {f: getattr(t, f) for f, _ in seeds_tuning._fields_}
+
+
 def seeds_get_tuning(ctx) -> dict:
     t = seeds_tuning()
     _check(lib().seeds_get_tuning(ctx, ctypes.byref(t)))
-    return {"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap}
+    return _tuning_dict(t)
 
 
-def seeds_set_tuning(ctx, pixel_compaction: int = 0, xcd_remap: int = 1) -> None:
-    t = seeds_tuning(pixel_compaction, xcd_remap)
+def seeds_set_tuning(ctx, pixel_compaction: int = 0, xcd_remap: int = 1,
+                     items_per_group: int = 1, init_rows: int = 16) -> None:
+    t = seeds_tuning(pixel_compaction, xcd_remap, items_per_group, init_rows)
     _check(lib().seeds_set_tuning(ctx, ctypes.byref(t)))
 
 
 def seeds_autotune(ctx, reps: int = 3, stream=None):
-    """Time the four launch mappings, keep the fastest; the context comes back
-    freshly initialised. Returns (chosen dict, medians in ms per variant)."""
+    """Time the launch mappings and initialisation tiles, keep the fastest; the
+    context comes back freshly initialised. Returns (chosen dict, medians in
+    ms per variant, SEEDS_TUNE_VARIANTS entries)."""
     t = seeds_tuning()
-    ms = (ctypes.c_float * 4)()
+    ms = (ctypes.c_float * SEEDS_TUNE_VARIANTS)()
     _check(lib().seeds_autotune(ctx, reps, ctypes.byref(t), ms, _stream(stream)))
-    return ({"pixel_compaction": t.pixel_compaction, "xcd_remap": t.xcd_remap},
-            [ms[i] for i in range(4)])
+    return _tuning_dict(t), [ms[i] for i in range(SEEDS_TUNE_VARIANTS)]
 
 
 def seeds_segment_noalloc(rgb: torch.Tensor, num_superpixels: int, params: seeds_params,

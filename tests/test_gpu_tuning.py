@@ -1,5 +1,6 @@
 """Launch-mapping tuning never changes a result: every setting gives the
 oracle's labels, and the autotuner leaves the context freshly initialised."""
+import functools
 import os
 import sys
 
@@ -29,7 +30,16 @@ def S():
     return seeds
 
 
-SETTINGS = [(1, 1), (0, 1), (1, 0), (0, 0)]
+# (pixel_compaction, xcd_remap, items_per_group, init_rows): every mapping
+# combination, each with one of the three initialisation tile heights
+SETTINGS = [(c, r, it, (8, 16, 32)[(2 * c + r + it) % 3])
+            for c in (1, 0) for r in (1, 0) for it in (1, 2, 4)]
+FIELDS = ("pixel_compaction", "xcd_remap", "items_per_group", "init_rows")
+
+
+@functools.lru_cache(maxsize=None)
+def _ref_481(rule):
+    return oracle.seeds(synth.single_481x321(), 200, 3, 5, 4, 1, rule)[0]
 
 
 @pytest.mark.parametrize("setting", SETTINGS)
@@ -38,11 +48,11 @@ def test_every_setting_matches_the_oracle(S, setting, rule):
     import torch
     _say(f"tuning {setting} rule {rule}")
     img = synth.single_481x321()
-    ref, _, _ = oracle.seeds(img, 200, 3, 5, 4, 1, rule)
+    ref = _ref_481(rule)
     ctx = S.seeds_init(torch.from_numpy(img).cuda(), 200, S.make_params(3, 5, 4, 1, rule))
     try:
         S.seeds_set_tuning(ctx, *setting)
-        assert S.seeds_get_tuning(ctx) == {"pixel_compaction": setting[0], "xcd_remap": setting[1]}
+        assert S.seeds_get_tuning(ctx) == dict(zip(FIELDS, setting))
         for mode in (0, 1):
             S.seeds_set_launch_mode(ctx, mode)
             S.seeds_reinit(ctx, torch.from_numpy(img).cuda())
@@ -85,8 +95,9 @@ def test_autotune_returns_a_fresh_context(S):
     try:
         S.seeds_refine(ctx)                        # state that autotune must discard
         chosen, ms = S.seeds_autotune(ctx, reps=2)
-        assert chosen in [{"pixel_compaction": a, "xcd_remap": b} for a, b in SETTINGS]
-        assert all(m > 0 for m in ms)
+        assert chosen["pixel_compaction"] in (0, 1) and chosen["xcd_remap"] in (0, 1)
+        assert chosen["items_per_group"] in (1, 2, 4) and chosen["init_rows"] in (8, 16, 32)
+        assert len(ms) == S.SEEDS_TUNE_VARIANTS and all(m > 0 for m in ms)
         assert S.seeds_get_tuning(ctx) == chosen
         assert S.seeds_level(ctx) == 2             # back at the top level
         S.seeds_refine(ctx)
@@ -94,10 +105,41 @@ def test_autotune_returns_a_fresh_context(S):
         S.seeds_labels(ctx, lab)
         ref, _, _ = oracle.seeds(img, 200, 3, 5, 4, 1, 0)
         assert np.array_equal(lab.numpy(), ref)
-        with pytest.raises(S.SeedsError):
-            S.seeds_set_tuning(ctx, 2, 1)
+        for bad in ((2, 1, 1, 16), (0, 1, 3, 16), (0, 1, 1, 12)):
+            with pytest.raises(S.SeedsError):
+                S.seeds_set_tuning(ctx, *bad)
         S.seeds_set_launch_mode(ctx, S.SEEDS_LAUNCH_PERSISTENT)
         with pytest.raises(S.SeedsError):
             S.seeds_autotune(ctx)
+    finally:
+        S.seeds_destroy(ctx)
+
+
+@pytest.mark.parametrize("rows", [8, 16, 32])
+@pytest.mark.parametrize("items", [1, 4])
+def test_warm_start_tiles(S, rows, items):
+    """The warm start (re-bin and recount per frame) with every tile height,
+    frame by frame against the oracle."""
+    import torch
+    _say(f"warm start rows {rows} items {items}")
+    sc = synth.StreamScene(H=180, W=250, regions=40, frames=3)
+    frames = [sc.frame(f) for f in range(3)]
+    ctx = S.seeds_init(torch.from_numpy(frames[0]).cuda(), 120, S.make_params(3, 5, 2, 1, 0))
+    o = oracle.Oracle(frames[0], 120, 3, 5, 2, 1, 0)
+    try:
+        S.seeds_set_tuning(ctx, 0, 1, items, rows)
+        S.seeds_reinit(ctx, torch.from_numpy(frames[0]).cuda())
+        for f in range(3):
+            if f:
+                S.seeds_warm_start(ctx, torch.from_numpy(frames[f]).cuda())
+                o.warm_start(frames[f])
+            S.seeds_refine(ctx)
+            o.run()
+            lab = torch.empty((180, 250), dtype=torch.int32)
+            S.seeds_labels(ctx, lab)
+            assert np.array_equal(lab.numpy(), o.labels()), f"frame {f}"
+            hist = torch.empty((S.seeds_num_superpixels(ctx), 125), dtype=torch.int32)
+            S.seeds_histograms(ctx, hist, None)
+            assert np.array_equal(hist.numpy(), o.histograms()[0]), f"frame {f}"
     finally:
         S.seeds_destroy(ctx)
