@@ -112,7 +112,8 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
     per_level = []
     for lvl in levels_walk:
         side = 1 << lvl
-        rec = {"side": side, "phases": 0, "boundary_pixels": 0, "pixels": 0, "moved_units": 0}
+        rec = {"side": side, "phases": 0, "boundary_pixels": 0, "pixels": 0, "moved_units": 0,
+               "bytes": 0.0}
         part = [i for i, (_, _, L) in enumerate(dims) if L - 1 >= lvl]
         for _ in range(iters):
             for cls in range(9):
@@ -135,6 +136,7 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
                         rec["moved_units"] += mv
                     lb = 2.0 if (lvl == 0 and lab16) else 4.0
                     total += lb * uw * uh / 9.0 + b[i][1] + lb * mv
+                    rec["bytes"] += lb * uw * uh / 9.0 + b[i][1] + lb * mv
                     struct += structural_phase_bytes(h, w, lvl, cls, lb)
                     rec["boundary_pixels"] += b[i][1]
         rec["pixels"] = sum(dims[i][0] * dims[i][1] for i in part)
@@ -145,6 +147,7 @@ def schedule_profile(S, ctx, dims, levels_walk, iters, moves=False, energy=False
             rec["H_prime"], rec["G_prime"] = h_e, g_e
             rec["E_prime"] = h_e + (GAMMA * g_e if lvl == 0 else 0)
         rec["moved_units"] = round(rec["moved_units"]) if moves else None
+        rec["algorithmic_bytes_per_launch"] = int(rec.pop("bytes") / max(1, rec["phases"]))
         per_level.append(rec)
     torch.cuda.synchronize()
     return {"launches": launches, "bytes": total, "bytes_per_launch": total / max(1, launches),
@@ -382,8 +385,7 @@ def apply_tuning(S, ctx, args):
     """--tuning c,r,items,rows: set that mapping (no autotuning)."""
     if not args.tuning:
         return None
-    c, r, it, rows = (int(v) for v in args.tuning.split(","))
-    S.seeds_set_tuning(ctx, c, r, it, rows)
+    S.seeds_set_tuning(ctx, *(int(v) for v in args.tuning.split(",")))
     return {"chosen": S.seeds_get_tuning(ctx), "set": True}
 
 
@@ -752,6 +754,7 @@ def run_serve(args) -> dict:
     params = S.seeds_server_default_params()
     params.iters_per_level, params.max_levels = ITERS, LEVELS
     params.hbm_budget_bytes, params.max_inflight = args.budget_gib << 30, 1024
+    params.items_per_group = args.serve_items
     srv = S.seeds_server_create(params, stream)
     done_at = np.full(total, np.nan)
     owner, out_of = {}, {}
@@ -853,6 +856,7 @@ def run_serve(args) -> dict:
                                "rule; labels to pinned host memory; continuous batching server "
                                f"with a {args.budget_gib} GiB budget",
                    "rate_req_s": rate, "offered_mpx_s": round(float(px.mean()) * rate / 1e6, 1),
+                   "items_per_group": args.serve_items,
                    "requests_timed": n_timed, "requests_warmup": n_warm,
                    "step": "one request, arrival to labels in host memory"},
         "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
@@ -1042,6 +1046,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=4000, help="serve: timed requests")
     ap.add_argument("--warm-requests", type=int, default=500, help="serve: warm-up requests")
     ap.add_argument("--budget-gib", type=int, default=8, help="serve: server memory budget")
+    ap.add_argument("--serve-items", type=int, default=2,
+                    help="serve: work items per workgroup of the server's phase launches")
     ap.add_argument("--cpu-serve-requests", type=int, default=200,
                     help="serve: requests of the trace replayed through the oracle workers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1050,7 +1056,7 @@ def main() -> int:
                          "(seeds_autotune) before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tuning", default=None,
-                    help="pixel_compaction,xcd_remap,items_per_group,init_rows to set instead of "
+                    help="pixel_compaction,xcd_remap,items_per_group,init_rows,warm_rows to set instead of "
                          "autotuning (for profiler runs of the tuned mapping)")
     ap.add_argument("--skip", default="", help="comma-separated nested workloads to leave out")
     ap.add_argument("--skip-byte-pass", action="store_true",

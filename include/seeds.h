@@ -215,14 +215,16 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  *                     phase launch takes; more items mean fewer, longer
  *                     workgroups.
  *   init_rows         8, 16 or 32: rows of the 64-column tiles of the
- *                     initialisation and warm-start kernels (2, 4 or 8
- *                     pixels per thread).
- * Default: pixel_compaction 0, xcd_remap 1, items_per_group 1, init_rows 16. */
+ *                     initialisation kernel (2, 4 or 8 pixels per thread).
+ *   warm_rows         8, 16 or 32: the same for the warm-start kernel.
+ * Default: pixel_compaction 0, xcd_remap 1, items_per_group 1, init_rows 16,
+ * warm_rows 16.                                                             */
 typedef struct {
     int32_t pixel_compaction;
     int32_t xcd_remap;
     int32_t items_per_group;
     int32_t init_rows;
+    int32_t warm_rows;
 } seeds_tuning;
 
 seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out);
@@ -232,16 +234,16 @@ seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t);
  * xcd_remap and items_per_group (12 variants) is timed on whole refinements
  * of the context's own images (reps runs after one warm-up that captures the
  * graph; median) and the fastest kept. Then init_rows (3 variants), timed on
- * initialisations with that mapping. The context is re-initialised before
- * every run and once more at the end, so it returns freshly initialised (as
- * after seeds_reinit); the call waits for the stream. *chosen and
- * ms_per_variant[SEEDS_TUNE_VARIANTS] (either may be NULL) receive the
- * choice and the medians: entry v < 12 is the mapping with items_per_group
- * = 1, 2, 4 for v / 4 = 0, 1, 2 and, within, v % 4 = 2 (1 - xcd_remap) +
- * (1 - pixel_compaction); entry 12 + r the initialisation with init_rows =
- * 8, 16, 32 for r = 0, 1, 2. Not for SEEDS_LAUNCH_PERSISTENT; reps in
- * [1,50].                                                                    */
-#define SEEDS_TUNE_VARIANTS 15
+ * initialisations, and warm_rows (3 variants), timed on warm starts of the
+ * same images after one refinement. The context is re-initialised at the end,
+ * so it returns freshly initialised (as after seeds_reinit); the call waits
+ * for the stream. *chosen and ms_per_variant[SEEDS_TUNE_VARIANTS] (either may
+ * be NULL) receive the choice and the medians: entry v < 12 is the mapping
+ * with items_per_group = 1, 2, 4 for v / 4 = 0, 1, 2 and, within,
+ * v % 4 = 2 (1 - xcd_remap) + (1 - pixel_compaction); entry 12 + r the
+ * initialisation and entry 15 + r the warm start with 8, 16, 32 rows for
+ * r = 0, 1, 2. Not for SEEDS_LAUNCH_PERSISTENT; reps in [1,50].              */
+#define SEEDS_TUNE_VARIANTS 18
 seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
                             float *ms_per_variant, void *hip_stream);
 
@@ -353,6 +355,7 @@ typedef struct {
     int32_t max_inflight;     /* most images refined together, [1,65536]          */
     int32_t pixel_compaction; /* launch mapping as in seeds_tuning (0 or 1)       */
     int32_t xcd_remap;        /* (0 or 1); results do not depend on either        */
+    int32_t items_per_group;  /* 1, 2 or 4, as in seeds_tuning                     */
 } seeds_server_params;
 
 typedef struct {
@@ -362,8 +365,8 @@ typedef struct {
 } seeds_server_stats;
 
 /* B = 5, I = 4, gamma = 1, max_levels = 4, 4 GiB, 512 images, no pixel
- * compaction and hardware workgroup order (the faster mapping measured for
- * mixed request traffic).                                                   */
+ * compaction, hardware workgroup order and two work items per workgroup (the
+ * mapping measured fastest for mixed request traffic).                      */
 seeds_status seeds_server_default_params(seeds_server_params *p);
 
 /* Create a server whose ticks run on hip_stream; allocates the budget once.  */

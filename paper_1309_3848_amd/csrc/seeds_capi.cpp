@@ -204,10 +204,12 @@ LaunchMap descend_launch(const seeds_ctx *ctx, int level) {
     if (ctx->nimg == 1) return {nullptr, descend_groups(ctx->imgs[0].d, level)};
     return ctx->descend_map[level];
 }
-LaunchMap init_launch(const seeds_ctx *ctx) {
-    if (ctx->nimg == 1) return {nullptr, init_groups(ctx->imgs[0].d, ctx->tune.init_rows)};
-    return ctx->init_map[row_index(ctx->tune.init_rows)];
+// Tiles of `rows` rows over every image (initialisation and warm start).
+LaunchMap tile_launch(const seeds_ctx *ctx, int rows) {
+    if (ctx->nimg == 1) return {nullptr, init_groups(ctx->imgs[0].d, rows)};
+    return ctx->init_map[row_index(rows)];
 }
+LaunchMap init_launch(const seeds_ctx *ctx) { return tile_launch(ctx, ctx->tune.init_rows); }
 
 // Level of image i's labels, and the unit grid holding them.
 int image_level(const seeds_ctx *ctx, int i) {
@@ -818,13 +820,13 @@ seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t
                                    "(refine the first frame to the end)", ctx->sched.level);
     st = set_images(ctx, rgb, pitch, s);
     if (st != SEEDS_OK) return st;
-    const LaunchMap m = init_launch(ctx);
+    const LaunchMap m = tile_launch(ctx, ctx->tune.warm_rows);
     hipError_t e = inject_fault(SEEDS_FAULT_LAUNCH)
                        ? hipErrorLaunchFailure
                        : launch_fill(ctx->ar.state[0], 0, 2 * ctx->state_elems, s);
     if (e == hipSuccess)
         e = launch_rehist(batch_args(ctx), ctx->imgs[0], ctx->rgb[0], ctx->pitch[0], m.map,
-                          ctx->d_rgb, ctx->d_pitch, m.groups, ctx->tune.init_rows, s);
+                          ctx->d_rgb, ctx->d_pitch, m.groups, ctx->tune.warm_rows, s);
     if (e != hipSuccess) return device_error(ctx, e, "warm start launch");
     ctx->sched.cur_level = -1;
     ctx->sched.cur_sweep = 0;
@@ -1253,6 +1255,7 @@ seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out) {
     out->xcd_remap = ctx->tune.xcd_remap ? 1 : 0;
     out->items_per_group = ctx->tune.items;
     out->init_rows = ctx->tune.init_rows;
+    out->warm_rows = ctx->tune.warm_rows;
     return SEEDS_OK;
 }
 
@@ -1265,10 +1268,13 @@ seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t) {
         return fail(SEEDS_E_INVAL, "items_per_group %d is not 1, 2 or 4", t->items_per_group);
     if (t->init_rows != 8 && t->init_rows != 16 && t->init_rows != 32)
         return fail(SEEDS_E_INVAL, "init_rows %d is not 8, 16 or 32", t->init_rows);
+    if (t->warm_rows != 8 && t->warm_rows != 16 && t->warm_rows != 32)
+        return fail(SEEDS_E_INVAL, "warm_rows %d is not 8, 16 or 32", t->warm_rows);
     ctx->tune.pixel_compact = t->pixel_compaction != 0;
     ctx->tune.xcd_remap = t->xcd_remap != 0;
     ctx->tune.items = t->items_per_group;
     ctx->tune.init_rows = t->init_rows;
+    ctx->tune.warm_rows = t->warm_rows;
     clear_graphs(ctx);
     return SEEDS_OK;
 }
@@ -1277,21 +1283,27 @@ seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t) {
 
 namespace {
 
+// What time_runs times.
+enum TimedOp { TIME_REFINE, TIME_INIT, TIME_WARM };
+
 // Median over reps timed runs (after one untimed warm-up, which also captures
-// the refinement graph) of a fresh initialisation (refine = false) or of the
-// whole refinement that follows one (refine = true).
-seeds_status time_runs(seeds_ctx *ctx, int reps, bool refine, hipEvent_t e0, hipEvent_t e1,
+// the refinement graph) of the whole refinement that follows an
+// initialisation, of a fresh initialisation, or of a warm start on the
+// context's own images (the context must be at pixel level).
+seeds_status time_runs(seeds_ctx *ctx, int reps, TimedOp op, hipEvent_t e0, hipEvent_t e1,
                        hipStream_t s, float *median) {
     std::vector<float> t;
     hipError_t e = hipSuccess;
     for (int r = 0; r <= reps; ++r) {
-        if (refine) {
+        if (op == TIME_REFINE) {
             seeds_status st = start_schedule(ctx, s);
             if (st != SEEDS_OK) return st;
         }
         e = hipEventRecord(e0, s);
         if (e != hipSuccess) break;
-        seeds_status st = refine ? run_schedule(ctx, -1, nullptr, s) : start_schedule(ctx, s);
+        seeds_status st = op == TIME_REFINE ? run_schedule(ctx, -1, nullptr, s)
+                          : op == TIME_INIT ? start_schedule(ctx, s)
+                                            : warm_start(ctx, ctx->rgb.data(), ctx->pitch.data(), s);
         if (st != SEEDS_OK) return st;
         e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1336,7 +1348,7 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
         ctx->tune.items = kItemChoices[v / 4];
         clear_graphs(ctx);
         float med = 0;
-        st = time_runs(ctx, reps, true, e0, e1, s, &med);
+        st = time_runs(ctx, reps, TIME_REFINE, e0, e1, s, &med);
         if (st != SEEDS_OK) break;
         if (ms_per_variant) ms_per_variant[v] = med;
         if (v == 0 || med < best_ms) {
@@ -1354,7 +1366,7 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
     for (int v = 0; v < 3 && st == SEEDS_OK; ++v) {
         ctx->tune.init_rows = kRowChoices[v];
         float med = 0;
-        st = time_runs(ctx, reps, false, e0, e1, s, &med);
+        st = time_runs(ctx, reps, TIME_INIT, e0, e1, s, &med);
         if (st != SEEDS_OK) break;
         if (ms_per_variant) ms_per_variant[12 + v] = med;
         if (v == 0 || med < best_ms) {
@@ -1362,10 +1374,27 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
             best_rows = v;
         }
     }
+    if (st == SEEDS_OK) ctx->tune.init_rows = kRowChoices[best_rows];
+    // the warm start: refine to pixel level once, then warm starts on the
+    // same images (each run restarts from the labels the last one left)
+    int best_warm = 1;
+    if (st == SEEDS_OK) st = start_schedule(ctx, s);
+    if (st == SEEDS_OK) st = run_schedule(ctx, -1, nullptr, s);
+    for (int v = 0; v < 3 && st == SEEDS_OK; ++v) {
+        ctx->tune.warm_rows = kRowChoices[v];
+        float med = 0;
+        st = time_runs(ctx, reps, TIME_WARM, e0, e1, s, &med);
+        if (st != SEEDS_OK) break;
+        if (ms_per_variant) ms_per_variant[15 + v] = med;
+        if (v == 0 || med < best_ms) {
+            best_ms = med;
+            best_warm = v;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SEEDS_OK) return st;
-    ctx->tune.init_rows = kRowChoices[best_rows];
+    ctx->tune.warm_rows = kRowChoices[best_warm];
     if (chosen) (void)seeds_get_tuning(ctx, chosen);
     return start_schedule(ctx, s);
 }

@@ -277,7 +277,8 @@ struct PhaseTuning {
     bool pixel_compact = false;  // pixel phases: pre-test and compaction
     bool xcd_remap = true;      // workgroups numbered in contiguous bands per XCD
     int items = 1;              // work items (pixel tiles, block rounds) per workgroup: 1, 2, 4
-    int init_rows = kInitTH;    // rows of an initialisation / warm-start tile: 8, 16, 32
+    int init_rows = kInitTH;    // rows of an initialisation tile: 8, 16, 32
+    int warm_rows = kInitTH;    // rows of a warm-start tile: 8, 16, 32
 };
 constexpr int kItemChoices[3] = {1, 2, 4};
 constexpr int kRowChoices[3] = {8, 16, 32};

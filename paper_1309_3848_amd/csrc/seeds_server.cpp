@@ -99,10 +99,10 @@ size_t pixel_bytes(const Dims &d) {
     return round_up(N, kGran) + round_up(N * 4, kGran) + 2 * round_up(blk * 4, kGran);
 }
 size_t state_elems(const Dims &d) { return round_up((size_t)d.K * d.hs + d.K, 64); }
-int max_phase_groups(const Dims &d) {
+int max_phase_groups(const Dims &d, int items) {
     int g = 0;
     for (int l = 0; l < d.L; ++l)
-        for (int c = 0; c < 9; ++c) g = std::max(g, phase_groups(d, l, c));
+        for (int c = 0; c < 9; ++c) g = std::max(g, phase_launch_groups(d, l, c, items));
     return g;
 }
 
@@ -215,6 +215,7 @@ seeds_status seeds_server_default_params(seeds_server_params *p) {
     p->max_inflight = 512;
     p->pixel_compaction = 0;
     p->xcd_remap = 0;
+    p->items_per_group = 2;
     return SEEDS_OK;
 }
 
@@ -238,11 +239,14 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
     if ((p->pixel_compaction != 0 && p->pixel_compaction != 1) ||
         (p->xcd_remap != 0 && p->xcd_remap != 1))
         return sfail(SEEDS_E_INVAL, "pixel_compaction and xcd_remap are 0 or 1");
+    if (p->items_per_group != 1 && p->items_per_group != 2 && p->items_per_group != 4)
+        return sfail(SEEDS_E_INVAL, "items_per_group %d is not 1, 2 or 4", p->items_per_group);
     seeds_server *sv = new (std::nothrow) seeds_server();
     if (!sv) return sfail(SEEDS_E_NOMEM, "host allocation failed");
     sv->p = *p;
     sv->tune.pixel_compact = p->pixel_compaction != 0;
     sv->tune.xcd_remap = p->xcd_remap != 0;
+    sv->tune.items = p->items_per_group;
     sv->s = (hipStream_t)hip_stream;
     hipError_t e = hipGetDevice(&sv->device);
     // log entries per workgroup and phase: the most any level can produce
@@ -250,6 +254,7 @@ seeds_status seeds_server_create(seeds_server **out, const seeds_server_params *
     dd.B = p->bins_per_channel;
     dd.nb = dd.B * dd.B * dd.B;
     for (int l = 0; l < p->max_levels; ++l) sv->log_cap = std::max(sv->log_cap, deltas_per_round(dd, l));
+    sv->log_cap *= p->items_per_group;  // a workgroup's log holds all its items
     // budget: 60% pixels, 8% histograms (two copies), 32% move logs
     const size_t budget = (size_t)p->hbm_budget_bytes;
     sv->px_size = round_up(budget / 100 * 60, kGran);
@@ -345,7 +350,7 @@ seeds_status seeds_server_submit(seeds_server *sv, const uint8_t *rgb, int32_t H
     d.T = 1 << (levels - 1);
     r->px_len = pixel_bytes(d);
     r->st_len = state_elems(d);
-    r->groups_max = max_phase_groups(d);
+    r->groups_max = max_phase_groups(d, sv->tune.items);
     if (r->px_len > sv->px_size || r->st_len > sv->st_size || r->groups_max > sv->g_cap) {
         delete r;
         return sfail(SEEDS_E_INVAL, "a %d x %d image does not fit the server's memory budget", W, H);
@@ -461,7 +466,7 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     int pixel_groups = 0, block_groups = 0, max_level = 0;
     for (auto &pr : phase_of) {
         if (pr.second.first != 0) continue;
-        const int gr = phase_groups(pr.first->d, 0, pr.second.second);
+        const int gr = phase_launch_groups(pr.first->d, 0, pr.second.second, sv->tune.items);
         if (gr == 0) continue;
         add(pr.first, 0, pr.second.second, pixel_groups, gr);
         pixel_groups += gr;
@@ -469,7 +474,8 @@ seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     const int block0 = n;
     for (auto &pr : phase_of) {
         if (pr.second.first == 0) continue;
-        const int gr = phase_groups(pr.first->d, pr.second.first, pr.second.second);
+        const int gr =
+            phase_launch_groups(pr.first->d, pr.second.first, pr.second.second, sv->tune.items);
         if (gr == 0) continue;
         add(pr.first, pr.second.first, pr.second.second, block_groups, gr);
         block_groups += gr;

@@ -45,7 +45,8 @@ class seeds_server_params(ctypes.Structure):
     _fields_ = [("bins_per_channel", ctypes.c_int32), ("iters_per_level", ctypes.c_int32),
                 ("gamma", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+                ("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("items_per_group", ctypes.c_int32)]
 
 
 class seeds_server_stats(ctypes.Structure):
@@ -56,10 +57,11 @@ class seeds_server_stats(ctypes.Structure):
 
 class seeds_tuning(ctypes.Structure):
     _fields_ = [("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("items_per_group", ctypes.c_int32), ("init_rows", ctypes.c_int32)]
+                ("items_per_group", ctypes.c_int32), ("init_rows", ctypes.c_int32),
+                ("warm_rows", ctypes.c_int32)]
 
 
-SEEDS_TUNE_VARIANTS = 15
+SEEDS_TUNE_VARIANTS = 18
 
 
 class seeds_quality(ctypes.Structure):
@@ -436,8 +438,8 @@ def seeds_get_tuning(ctx) -> dict:
 
 
 def seeds_set_tuning(ctx, pixel_compaction: int = 0, xcd_remap: int = 1,
-                     items_per_group: int = 1, init_rows: int = 16) -> None:
-    t = seeds_tuning(pixel_compaction, xcd_remap, items_per_group, init_rows)
+                     items_per_group: int = 1, init_rows: int = 16, warm_rows: int = 16) -> None:
+    t = seeds_tuning(pixel_compaction, xcd_remap, items_per_group, init_rows, warm_rows)
     _check(lib().seeds_set_tuning(ctx, ctypes.byref(t)))
 
 

@@ -206,7 +206,7 @@ def test_server_argument_checks(S):
     srv = ctypes.c_void_p()
     for field, bad in (("bins_per_channel", 7), ("iters_per_level", 0), ("gamma", -1),
                        ("max_levels", 9), ("max_inflight", 0), ("hbm_budget_bytes", 1 << 20),
-                       ("pixel_compaction", 2), ("xcd_remap", -1)):
+                       ("pixel_compaction", 2), ("xcd_remap", -1), ("items_per_group", 3)):
         q = S.seeds_server_default_params()
         setattr(q, field, bad)
         assert L.seeds_server_create(ctypes.byref(srv), ctypes.byref(q), None) == S.SEEDS_E_INVAL

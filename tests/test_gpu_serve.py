@@ -75,10 +75,12 @@ def _serve(S, reqs, arrivals, params, host_out=False, max_ticks=100000, pageable
     return [o.cpu().numpy() for o in outs], stats
 
 
-def _params(S, budget=1 << 30, inflight=64, I=3, levels=4, mapping=None):
+def _params(S, budget=1 << 30, inflight=64, I=3, levels=4, mapping=None, items=None):
     p = S.seeds_server_default_params()
     if mapping is not None:
         p.pixel_compaction, p.xcd_remap = mapping
+    if items is not None:
+        p.items_per_group = items
     p.iters_per_level = I
     p.max_levels = levels
     p.hbm_budget_bytes = budget
@@ -96,12 +98,13 @@ def _requests(shapes, seed0=500):
     return imgs, [(torch.from_numpy(im).cuda(), K, L) for im, (_, _, _, K, L) in zip(imgs, shapes)]
 
 
-@pytest.mark.parametrize("mapping", [(0, 0), (1, 1), (0, 1), (1, 0)])
-def test_staggered_arrivals_match_solo_and_oracle(S, mapping):
-    _say(f"serve staggered {mapping}")
+@pytest.mark.parametrize("mapping,items", [((0, 0), 1), ((1, 1), 1), ((0, 1), 2), ((1, 0), 4),
+                                           ((0, 0), 2), ((1, 1), 4)])
+def test_staggered_arrivals_match_solo_and_oracle(S, mapping, items):
+    _say(f"serve staggered {mapping} items {items}")
     imgs, reqs = _requests(SHAPES)
     arrivals = [0, 3, 17, 40, 41, 90]          # several join mid-hierarchy of others
-    got, stats = _serve(S, reqs, arrivals, _params(S, mapping=mapping))
+    got, stats = _serve(S, reqs, arrivals, _params(S, mapping=mapping, items=items))
     assert stats["completed"] == len(reqs) and stats["peak_inflight"] >= 2
     for i, (im, (_, _, _, K, L)) in enumerate(zip(imgs, SHAPES)):
         ref, _, _ = oracle.seeds(im, K, L, 5, 3, 1, 0)

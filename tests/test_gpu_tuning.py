@@ -32,9 +32,9 @@ def S():
 
 # (pixel_compaction, xcd_remap, items_per_group, init_rows): every mapping
 # combination, each with one of the three initialisation tile heights
-SETTINGS = [(c, r, it, (8, 16, 32)[(2 * c + r + it) % 3])
+SETTINGS = [(c, r, it, (8, 16, 32)[(2 * c + r + it) % 3], (8, 16, 32)[(c + it) % 3])
             for c in (1, 0) for r in (1, 0) for it in (1, 2, 4)]
-FIELDS = ("pixel_compaction", "xcd_remap", "items_per_group", "init_rows")
+FIELDS = ("pixel_compaction", "xcd_remap", "items_per_group", "init_rows", "warm_rows")
 
 
 @functools.lru_cache(maxsize=None)
@@ -97,6 +97,7 @@ def test_autotune_returns_a_fresh_context(S):
         chosen, ms = S.seeds_autotune(ctx, reps=2)
         assert chosen["pixel_compaction"] in (0, 1) and chosen["xcd_remap"] in (0, 1)
         assert chosen["items_per_group"] in (1, 2, 4) and chosen["init_rows"] in (8, 16, 32)
+        assert chosen["warm_rows"] in (8, 16, 32)
         assert len(ms) == S.SEEDS_TUNE_VARIANTS and all(m > 0 for m in ms)
         assert S.seeds_get_tuning(ctx) == chosen
         assert S.seeds_level(ctx) == 2             # back at the top level
@@ -105,7 +106,7 @@ def test_autotune_returns_a_fresh_context(S):
         S.seeds_labels(ctx, lab)
         ref, _, _ = oracle.seeds(img, 200, 3, 5, 4, 1, 0)
         assert np.array_equal(lab.numpy(), ref)
-        for bad in ((2, 1, 1, 16), (0, 1, 3, 16), (0, 1, 1, 12)):
+        for bad in ((2, 1, 1, 16, 16), (0, 1, 3, 16, 16), (0, 1, 1, 12, 16), (0, 1, 1, 16, 7)):
             with pytest.raises(S.SeedsError):
                 S.seeds_set_tuning(ctx, *bad)
         S.seeds_set_launch_mode(ctx, S.SEEDS_LAUNCH_PERSISTENT)
@@ -127,7 +128,7 @@ def test_warm_start_tiles(S, rows, items):
     ctx = S.seeds_init(torch.from_numpy(frames[0]).cuda(), 120, S.make_params(3, 5, 2, 1, 0))
     o = oracle.Oracle(frames[0], 120, 3, 5, 2, 1, 0)
     try:
-        S.seeds_set_tuning(ctx, 0, 1, items, rows)
+        S.seeds_set_tuning(ctx, 0, 1, items, 16, rows)
         S.seeds_reinit(ctx, torch.from_numpy(frames[0]).cuda())
         for f in range(3):
             if f:
