@@ -22,6 +22,7 @@
 
 #include "seeds.h"
 #include "seeds_internal.h"
+#include "seeds_trace.h"
 
 using namespace seeds;
 
@@ -222,6 +223,7 @@ const int32_t *image_grid(const seeds_ctx *ctx, int i) {
 }
 
 seeds_status start_schedule(seeds_ctx *ctx, hipStream_t s) {
+    TraceRange tr("seeds init");
     const LaunchMap m = init_launch(ctx);
     // both state copies (histograms, then sizes, of every image) are contiguous
     hipError_t e = inject_fault(SEEDS_FAULT_LAUNCH)
@@ -258,12 +260,27 @@ hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_pha
     uint32_t stamp = 0;
     hipError_t e = hipSuccess;
     if (exact) e = launch_fill(b.ar.src, 0, a.src_elems, s);
+    // one range per level (opened at the level's first operation)
+    int traced_level = -1;
+    bool range_open = false;
     for (;;) {
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess) break;
         int cls = 0;
         const SchedOp op = sched_next(top, sched, max_phases < 0 ? -1 : max_phases - done, &cls);
         if (op == OP_END) break;
-        if (inject_fault(SEEDS_FAULT_LAUNCH)) return hipErrorLaunchFailure;
+        if (inject_fault(SEEDS_FAULT_LAUNCH)) {
+            e = hipErrorLaunchFailure;
+            break;
+        }
+        const int lv = op == OP_DESCEND ? sched.level - 1 : sched.level;
+        if (a.trace && lv != traced_level) {
+            if (range_open) roctxRangePop();
+            char name[48];
+            snprintf(name, sizeof(name), "seeds level %d (unit side %d)", lv, 1 << lv);
+            roctxRangePushA(name);
+            range_open = true;
+            traced_level = lv;
+        }
         if (op == OP_DESCEND) {
             const LaunchMap m = a.phase_map ? a.descend_map[sched.level]
                                             : LaunchMap{nullptr, descend_groups(one.d, sched.level)};
@@ -299,6 +316,7 @@ hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_pha
         }
         sched_done(sched, op);
     }
+    if (range_open) roctxRangePop();
     if (e == hipSuccess && prev_groups > 0) e = launch_final_replay(b, par ^ 1, prev_groups, s);
     if (e == hipSuccess && done_out) *done_out = done;
     return e;
@@ -369,6 +387,7 @@ seeds_status run_graph(seeds_ctx *ctx, int32_t *done_out, hipStream_t s) {
 }
 
 seeds_status run_schedule(seeds_ctx *ctx, int32_t max_phases, int32_t *done_out, hipStream_t s) {
+    TraceRange tr("seeds refine");
     const Dims &top = ctx->top;
     if (!ctx->cold && ctx->sched.cur_level < 0) {  // finished: another I pixel sweeps
         ctx->sched.cur_level = 0;
@@ -813,6 +832,7 @@ seeds_status set_images(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t
 // the schedule marked finished so that the next refine runs I pixel sweeps.
 seeds_status warm_start(seeds_ctx *ctx, const uint8_t *const *rgb, const int64_t *pitch,
                         hipStream_t s) {
+    TraceRange tr("seeds warm start");
     seeds_status st = check_usable(ctx);
     if (st != SEEDS_OK) return st;
     if (ctx->sched.level != 0)

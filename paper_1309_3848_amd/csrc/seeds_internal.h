@@ -365,6 +365,7 @@ struct ScheduleArgs {
     const LaunchMap *descend_map = nullptr;
     int64_t src_elems = 0;
     PhaseTuning tune;
+    bool trace = true;  // roctx ranges per level (host side)
 };
 
 // Enqueue the schedule from the cursor `sched` as per-phase launches (at most

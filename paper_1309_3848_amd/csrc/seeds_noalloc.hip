@@ -122,6 +122,7 @@ extern "C" seeds_status seeds_segment_noalloc(const uint8_t *rgb, int32_t H, int
     a.one.bl[1] = o.bl_elems;
     a.top = d;
     a.src_elems = o.src_elems;
+    a.trace = false;  // nothing but kernel launches on this path
     BatchArgs &b = a.b;
     b.imgs = nullptr;  // single-image kernels take the image from `one`
     b.nimg = 1;

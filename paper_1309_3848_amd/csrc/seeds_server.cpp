@@ -23,6 +23,7 @@
 
 #include "seeds.h"
 #include "seeds_internal.h"
+#include "seeds_trace.h"
 
 using namespace seeds;
 
@@ -385,6 +386,7 @@ seeds_status seeds_server_submit(seeds_server *sv, const uint8_t *rgb, int32_t H
 
 seeds_status seeds_server_step(seeds_server *sv, int32_t *pending) {
     if (!sv) return sfail(SEEDS_E_INVAL, "server is NULL");
+    TraceRange tr("seeds server tick %d", (int)sv->tick);
     if (sv->poisoned) return sfail(SEEDS_E_STATE, "server is poisoned by an earlier device error");
     hipStream_t s = sv->s;
     const int64_t t = sv->tick;
