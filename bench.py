@@ -382,7 +382,8 @@ def run_single(args, img, k, levels, name, steps, warmup, traffic_file=None, lds
 
 
 def apply_tuning(S, ctx, args):
-    """--tuning c,r,items,rows: set that mapping (no autotuning)."""
+    """--tuning c,r,items,init_rows,warm_rows[,block_ppl]: set that mapping (no
+    autotuning)."""
     if not args.tuning:
         return None
     S.seeds_set_tuning(ctx, *(int(v) for v in args.tuning.split(",")))
@@ -1056,7 +1057,8 @@ def main() -> int:
                          "(seeds_autotune) before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tuning", default=None,
-                    help="pixel_compaction,xcd_remap,items_per_group,init_rows,warm_rows to set instead of "
+                    help="pixel_compaction,xcd_remap,items_per_group,init_rows,warm_rows[,block_ppl] "
+                         "to set instead of "
                          "autotuning (for profiler runs of the tuned mapping)")
     ap.add_argument("--skip", default="", help="comma-separated nested workloads to leave out")
     ap.add_argument("--skip-byte-pass", action="store_true",

@@ -217,33 +217,42 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  *   init_rows         8, 16 or 32: rows of the 64-column tiles of the
  *                     initialisation kernel (2, 4 or 8 pixels per thread).
  *   warm_rows         8, 16 or 32: the same for the warm-start kernel.
+ *   block_ppl         1 or 4: pixels of a block each lane holds in the block
+ *                     phases of block sides 2, 4 and 8 (1: 4, 16 and 64
+ *                     lanes per block; 4: 1, 4 and 16 lanes, so a wavefront
+ *                     decides four times as many blocks at once). Larger
+ *                     blocks always take 64 lanes.
  * Default: pixel_compaction 0, xcd_remap 1, items_per_group 1, init_rows 16,
- * warm_rows 16.                                                             */
+ * warm_rows 16, block_ppl 1.                                                */
 typedef struct {
     int32_t pixel_compaction;
     int32_t xcd_remap;
     int32_t items_per_group;
     int32_t init_rows;
     int32_t warm_rows;
+    int32_t block_ppl;
 } seeds_tuning;
 
 seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out);
 seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t);
 
 /* Autotuner. First the phase mapping: every combination of pixel_compaction,
- * xcd_remap and items_per_group (12 variants) is timed on whole refinements
- * of the context's own images (reps runs after one warm-up that captures the
- * graph; median) and the fastest kept. Then init_rows (3 variants), timed on
- * initialisations, and warm_rows (3 variants), timed on warm starts of the
- * same images after one refinement. The context is re-initialised at the end,
- * so it returns freshly initialised (as after seeds_reinit); the call waits
- * for the stream. *chosen and ms_per_variant[SEEDS_TUNE_VARIANTS] (either may
- * be NULL) receive the choice and the medians: entry v < 12 is the mapping
- * with items_per_group = 1, 2, 4 for v / 4 = 0, 1, 2 and, within,
- * v % 4 = 2 (1 - xcd_remap) + (1 - pixel_compaction); entry 12 + r the
- * initialisation and entry 15 + r the warm start with 8, 16, 32 rows for
+ * xcd_remap and items_per_group (12 variants, block_ppl 1) is timed on whole
+ * refinements of the context's own images (reps runs after one warm-up that
+ * captures the graph; median). Then block_ppl 4 with each items_per_group and
+ * the compaction and remap of the fastest so far (3 variants); the fastest of
+ * the 15 is kept. Then init_rows (3 variants), timed on initialisations, and
+ * warm_rows (3 variants), timed on warm starts of the same images after one
+ * refinement. The context is re-initialised at the end, so it returns freshly
+ * initialised (as after seeds_reinit); the call waits for the stream.
+ * *chosen and ms_per_variant[SEEDS_TUNE_VARIANTS] (either may be NULL)
+ * receive the choice and the medians: entry v < 12 is the mapping with
+ * items_per_group = 1, 2, 4 for v / 4 = 0, 1, 2 and, within,
+ * v % 4 = 2 (1 - xcd_remap) + (1 - pixel_compaction); entry 12 + i block_ppl
+ * 4 with items_per_group 1, 2, 4 for i = 0, 1, 2; entry 15 + r the
+ * initialisation and entry 18 + r the warm start with 8, 16, 32 rows for
  * r = 0, 1, 2. Not for SEEDS_LAUNCH_PERSISTENT; reps in [1,50].              */
-#define SEEDS_TUNE_VARIANTS 18
+#define SEEDS_TUNE_VARIANTS 21
 seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
                             float *ms_per_variant, void *hip_stream);
 

@@ -94,13 +94,14 @@ struct seeds_ctx {
     int64_t *d_pitch = nullptr;       // batch: device table of row pitches
     std::vector<const uint8_t *> rgb;  // host copies of the two tables
     std::vector<int64_t> pitch;
-    // batch maps, one set per tuning choice of items per workgroup / init rows
-    std::vector<LaunchMap> phase_map[3];  // batch: [item choice][level * 9 + cls]
-    std::vector<LaunchMap> descend_map;   // batch: [level]
-    LaunchMap init_map[3];                // batch: [row choice]
-    // move-log shape of the per-phase launches for each items-per-workgroup
-    // choice (the slab holds the largest)
-    int log_groups_of[3] = {1, 1, 1}, log_cap_of[3] = {1, 1, 1};
+    // batch maps, one set per tuning choice of items per workgroup and block
+    // pixels per lane / of init rows
+    std::vector<LaunchMap> phase_map[3][2];  // batch: [item choice][ppl choice][level * 9 + cls]
+    std::vector<LaunchMap> descend_map;      // batch: [level]
+    LaunchMap init_map[3];                   // batch: [row choice]
+    // move-log shape of the per-phase launches for each choice of items per
+    // workgroup and block pixels per lane (the slab holds the largest)
+    int log_groups_of[3][2] = {{1, 1}, {1, 1}, {1, 1}}, log_cap_of[3][2] = {{1, 1}, {1, 1}, {1, 1}};
     PersistentGeom geom{};            // single image only
     int mode = SEEDS_LAUNCH_GRAPH;    // seeds_launch_mode
     PhaseTuning tune;                 // mapping of the per-phase launches
@@ -193,10 +194,11 @@ BatchArgs batch_args(const seeds_ctx *ctx) {
     b.imgs = ctx->d_imgs;
     b.nimg = ctx->nimg;
     b.ar = ctx->ar;
-    const int it = item_index(ctx->tune.items);
-    b.log_cap = ctx->log_cap_of[it];
-    b.log_groups = ctx->log_groups_of[it];
+    const int it = item_index(ctx->tune.items), pp = ppl_index(ctx->tune.block_ppl);
+    b.log_cap = ctx->log_cap_of[it][pp];
+    b.log_groups = ctx->log_groups_of[it][pp];
     b.items = ctx->tune.items;
+    b.bppl = ctx->tune.block_ppl;
     return b;
 }
 
@@ -289,7 +291,8 @@ hipError_t enqueue_schedule(const ScheduleArgs &a, Sched &sched, int32_t max_pha
             const int level = sched.level;
             const LaunchMap m =
                 a.phase_map ? a.phase_map[level * 9 + cls]
-                            : LaunchMap{nullptr, phase_launch_groups(one.d, level, cls, a.tune.items)};
+                            : LaunchMap{nullptr, phase_launch_groups(one.d, level, cls, a.tune.items,
+                                                                     a.tune.block_ppl)};
             ++stamp;
             if (m.groups == 0) {
                 // no unit of this class in any image: nothing moves; the
@@ -331,7 +334,9 @@ seeds_status enqueue_phases(seeds_ctx *ctx, int32_t max_phases, int32_t *done_ou
     a.b = batch_args(ctx);
     a.one = ctx->imgs[0];
     a.top = ctx->top;
-    a.phase_map = ctx->nimg > 1 ? ctx->phase_map[item_index(ctx->tune.items)].data() : nullptr;
+    a.phase_map = ctx->nimg > 1
+                      ? ctx->phase_map[item_index(ctx->tune.items)][ppl_index(ctx->tune.block_ppl)].data()
+                      : nullptr;
     a.descend_map = ctx->nimg > 1 ? ctx->descend_map.data() : nullptr;
     a.src_elems = ctx->src_elems;
     a.tune = ctx->tune;
@@ -535,17 +540,24 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     ctx->src_elems = (int64_t)src;
     // workgroup maps of a batch
     std::vector<int2> maps;
-    std::vector<std::pair<size_t, int>> phase_pos[3], descend_pos(Lmax);
+    std::vector<std::pair<size_t, int>> phase_pos[3][2], descend_pos(Lmax);
     std::pair<size_t, int> init_pos[3];
     if (ctx->nimg > 1) {
-        for (int v = 0; v < 3; ++v) {
-            phase_pos[v].resize(Lmax * 9);
-            for (int l = 0; l < Lmax; ++l)
-                for (int c = 0; c < 9; ++c)
-                    phase_pos[v][l * 9 + c] = append_map(maps, ctx->imgs, l, [&](const Dims &d) {
-                        return phase_launch_groups(d, l, c, kItemChoices[v]);
-                    });
-        }
+        for (int v = 0; v < 3; ++v)
+            for (int p = 0; p < 2; ++p) {
+                phase_pos[v][p].resize(Lmax * 9);
+                for (int l = 0; l < Lmax; ++l)
+                    for (int c = 0; c < 9; ++c) {
+                        if (p == 1 && (l == 0 || l > 3)) {  // the same as one pixel per lane
+                            phase_pos[v][p][l * 9 + c] = phase_pos[v][0][l * 9 + c];
+                            continue;
+                        }
+                        phase_pos[v][p][l * 9 + c] =
+                            append_map(maps, ctx->imgs, l, [&](const Dims &d) {
+                                return phase_launch_groups(d, l, c, kItemChoices[v], kPplChoices[p]);
+                            });
+                    }
+            }
         for (int l = 1; l < Lmax; ++l)
             descend_pos[l] =
                 append_map(maps, ctx->imgs, l, [&](const Dims &d) { return descend_groups(d, l); });
@@ -557,23 +569,27 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     // as the most deltas one workgroup of any image can produce in a phase
     // (per choice of work items per workgroup: a workgroup's log holds the
     // deltas of all its items)
-    int round_cap = 1;
-    for (const auto &g : ctx->imgs)
-        for (int l = 0; l < g.d.L; ++l) round_cap = std::max(round_cap, deltas_per_round(g.d, l));
     size_t log_entries = 0, log_slots = 0;
-    for (int v = 0; v < 3; ++v) {
-        int groups = 1;
-        for (int l = 0; l < Lmax; ++l)
-            for (int c = 0; c < 9; ++c) {
-                int n = 0;
-                for (const auto &g : ctx->imgs)
-                    if (g.d.L - 1 >= l) n += phase_launch_groups(g.d, l, c, kItemChoices[v]);
-                groups = std::max(groups, n);
-            }
-        ctx->log_groups_of[v] = groups;
-        ctx->log_cap_of[v] = round_cap * kItemChoices[v];
-        log_entries = std::max(log_entries, (size_t)groups * ctx->log_cap_of[v]);
-        log_slots = std::max(log_slots, (size_t)groups);
+    for (int p = 0; p < 2; ++p) {
+        int round_cap = 1;
+        for (const auto &g : ctx->imgs)
+            for (int l = 0; l < g.d.L; ++l)
+                round_cap = std::max(round_cap, deltas_per_round(g.d, l, kPplChoices[p]));
+        for (int v = 0; v < 3; ++v) {
+            int groups = 1;
+            for (int l = 0; l < Lmax; ++l)
+                for (int c = 0; c < 9; ++c) {
+                    int n = 0;
+                    for (const auto &g : ctx->imgs)
+                        if (g.d.L - 1 >= l)
+                            n += phase_launch_groups(g.d, l, c, kItemChoices[v], kPplChoices[p]);
+                    groups = std::max(groups, n);
+                }
+            ctx->log_groups_of[v][p] = groups;
+            ctx->log_cap_of[v][p] = round_cap * kItemChoices[v];
+            log_entries = std::max(log_entries, (size_t)groups * ctx->log_cap_of[v][p]);
+            log_slots = std::max(log_slots, (size_t)groups);
+        }
     }
     if (ctx->nimg == 1) ctx->geom = persistent_geometry(in[0].d, ctx->device, 2);
     log_entries = std::max(log_entries, (size_t)ctx->geom.groups * ctx->geom.log_cap);
@@ -629,9 +645,12 @@ seeds_status create_ctx(seeds_ctx **out, const std::vector<ImageIn> &in, hipStre
     const int2 *d_maps = (const int2 *)(base + o_maps);
     if (ctx->nimg > 1) {
         for (int v = 0; v < 3; ++v) {
-            ctx->phase_map[v].resize(Lmax * 9);
-            for (int i = 0; i < Lmax * 9; ++i)
-                ctx->phase_map[v][i] = {d_maps + phase_pos[v][i].first, phase_pos[v][i].second};
+            for (int p = 0; p < 2; ++p) {
+                ctx->phase_map[v][p].resize(Lmax * 9);
+                for (int i = 0; i < Lmax * 9; ++i)
+                    ctx->phase_map[v][p][i] = {d_maps + phase_pos[v][p][i].first,
+                                               phase_pos[v][p][i].second};
+            }
             ctx->init_map[v] = {d_maps + init_pos[v].first, init_pos[v].second};
         }
         ctx->descend_map.resize(Lmax);
@@ -1276,6 +1295,7 @@ seeds_status seeds_get_tuning(const seeds_ctx *ctx, seeds_tuning *out) {
     out->items_per_group = ctx->tune.items;
     out->init_rows = ctx->tune.init_rows;
     out->warm_rows = ctx->tune.warm_rows;
+    out->block_ppl = ctx->tune.block_ppl;
     return SEEDS_OK;
 }
 
@@ -1290,11 +1310,14 @@ seeds_status seeds_set_tuning(seeds_ctx *ctx, const seeds_tuning *t) {
         return fail(SEEDS_E_INVAL, "init_rows %d is not 8, 16 or 32", t->init_rows);
     if (t->warm_rows != 8 && t->warm_rows != 16 && t->warm_rows != 32)
         return fail(SEEDS_E_INVAL, "warm_rows %d is not 8, 16 or 32", t->warm_rows);
+    if (t->block_ppl != 1 && t->block_ppl != 4)
+        return fail(SEEDS_E_INVAL, "block_ppl %d is not 1 or 4", t->block_ppl);
     ctx->tune.pixel_compact = t->pixel_compaction != 0;
     ctx->tune.xcd_remap = t->xcd_remap != 0;
     ctx->tune.items = t->items_per_group;
     ctx->tune.init_rows = t->init_rows;
     ctx->tune.warm_rows = t->warm_rows;
+    ctx->tune.block_ppl = t->block_ppl;
     clear_graphs(ctx);
     return SEEDS_OK;
 }
@@ -1357,11 +1380,14 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
         if (e0) (void)hipEventDestroy(e0);
         return device_error(ctx, e, "hipEventCreate");
     }
-    // the phase mapping (compaction x remap x items per workgroup), timed on
-    // whole refinements; then the rows of the initialisation tiles, timed on
-    // initialisations with the chosen mapping
+    // the phase mapping (compaction x remap x items per workgroup, one pixel
+    // per lane in block phases), timed on whole refinements; then four pixels
+    // per lane with each choice of items and the chosen compaction and remap;
+    // then the rows of the initialisation tiles, timed on initialisations
+    // with the chosen mapping
     float best_ms = 0;
     int best = 0;
+    ctx->tune.block_ppl = 1;
     for (int v = 0; v < 12 && st == SEEDS_OK; ++v) {
         ctx->tune.pixel_compact = (v & 1) == 0;
         ctx->tune.xcd_remap = (v & 2) == 0;
@@ -1379,7 +1405,25 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
     if (st == SEEDS_OK) {
         ctx->tune.pixel_compact = (best & 1) == 0;
         ctx->tune.xcd_remap = (best & 2) == 0;
-        ctx->tune.items = kItemChoices[best / 4];
+    }
+    int best_items = best / 4, best_ppl = 0;
+    for (int v = 0; v < 3 && st == SEEDS_OK; ++v) {
+        ctx->tune.items = kItemChoices[v];
+        ctx->tune.block_ppl = 4;
+        clear_graphs(ctx);
+        float med = 0;
+        st = time_runs(ctx, reps, TIME_REFINE, e0, e1, s, &med);
+        if (st != SEEDS_OK) break;
+        if (ms_per_variant) ms_per_variant[12 + v] = med;
+        if (med < best_ms) {
+            best_ms = med;
+            best_items = v;
+            best_ppl = 1;
+        }
+    }
+    if (st == SEEDS_OK) {
+        ctx->tune.items = kItemChoices[best_items];
+        ctx->tune.block_ppl = kPplChoices[best_ppl];
         clear_graphs(ctx);
     }
     int best_rows = 1;
@@ -1388,7 +1432,7 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
         float med = 0;
         st = time_runs(ctx, reps, TIME_INIT, e0, e1, s, &med);
         if (st != SEEDS_OK) break;
-        if (ms_per_variant) ms_per_variant[12 + v] = med;
+        if (ms_per_variant) ms_per_variant[15 + v] = med;
         if (v == 0 || med < best_ms) {
             best_ms = med;
             best_rows = v;
@@ -1405,7 +1449,7 @@ seeds_status seeds_autotune(seeds_ctx *ctx, int32_t reps, seeds_tuning *chosen,
         float med = 0;
         st = time_runs(ctx, reps, TIME_WARM, e0, e1, s, &med);
         if (st != SEEDS_OK) break;
-        if (ms_per_variant) ms_per_variant[15 + v] = med;
+        if (ms_per_variant) ms_per_variant[18 + v] = med;
         if (v == 0 || med < best_ms) {
             best_ms = med;
             best_warm = v;

@@ -167,27 +167,52 @@ struct BatchArgs {
     int log_cap;
     int log_groups;
     int items = 1;  // phase work items per workgroup (batch maps count workgroups with it)
+    int bppl = 1;   // pixels per lane of the block levels 1-3 (1 or 4; batch maps count with it)
 };
 
 constexpr int kPersistentThreads = 256;
 
 // Segment shape of block level l (side s = 2^l): SEG lanes per block, PPL
-// pixels per lane, SEG * PPL = s * s.
-__host__ __device__ inline int seg_lanes(int level) { return level >= 3 ? 64 : 1 << (2 * level); }
-__host__ __device__ inline int seg_ppl(int level) { return level >= 3 ? 1 << (2 * level - 6) : 1; }
+// pixels per lane, SEG * PPL = s * s. bppl (a tuning choice) is the number
+// of pixels per lane at levels 1-3: 1 gives one lane per pixel (at most one
+// block per wavefront at side 8), 4 gives four times as many blocks per
+// wavefront, whose loads are then in flight together. Larger blocks always
+// take 64 lanes.
+__host__ __device__ inline int seg_lanes(int level, int bppl = 1) {
+    if (bppl == 4 && level <= 3) return 1 << (2 * level - 2);
+    return level >= 3 ? 64 : 1 << (2 * level);
+}
+__host__ __device__ inline int seg_ppl(int level, int bppl = 1) {
+    if (bppl == 4 && level <= 3) return 4;
+    return level >= 3 ? 1 << (2 * level - 6) : 1;
+}
+// How a segment finds the count h_l(j) of each bin j of its block:
+//   0 in registers (shuffles among at most 16 pixels),
+//   1 in one LDS histogram row per segment (16 to 64 pixels),
+//   2 from the block's bins staged in LDS (more than 64 pixels).
+__host__ __device__ constexpr int bin_count_kind(int seg, int ppl) {
+    if (seg == 64 && ppl > 1) return 2;
+    return seg * ppl > 16 || seg >= 16 ? 1 : 0;
+}
 
-// Dynamic LDS of a block phase at `level` (hs: histogram row stride): blocks
-// of more than 64 pixels stage their bins (one byte per pixel), blocks of 16
-// to 64 pixels count their bins in one LDS histogram row per segment.
-__host__ __device__ inline int phase_lds_bytes(int level, int hs) {
+// Dynamic LDS of a block phase at `level` (hs: histogram row stride): the
+// staged bins (one byte per pixel) or the histogram rows.
+__host__ __device__ inline int phase_lds_bytes(int level, int hs, int bppl = 1) {
     if (level == 0) return 0;
-    if (seg_ppl(level) > 1) return kPersistentThreads * seg_ppl(level);
-    return seg_lanes(level) >= 16 ? (kPersistentThreads / seg_lanes(level)) * hs * 4 : 0;
+    const int seg = seg_lanes(level, bppl), ppl = seg_ppl(level, bppl);
+    switch (bin_count_kind(seg, ppl)) {
+        case 2: return kPersistentThreads * ppl;
+        case 1: return (kPersistentThreads / seg) * hs * 4;
+        default: return 0;
+    }
 }
 // The most any level up to max_level needs.
-__host__ __device__ inline int phase_lds_bytes_upto(int max_level, int hs) {
+__host__ __device__ inline int phase_lds_bytes_upto(int max_level, int hs, int bppl = 1) {
     int b = 0;
-    for (int l = 1; l <= max_level; ++l) b = b > phase_lds_bytes(l, hs) ? b : phase_lds_bytes(l, hs);
+    for (int l = 1; l <= max_level; ++l) {
+        const int x = phase_lds_bytes(l, hs, bppl);
+        b = b > x ? b : x;
+    }
     return b;
 }
 
@@ -207,23 +232,24 @@ __host__ __device__ inline int pixel_tiles(const Dims &d, int cls) {
 // Work items of one phase of class cls for an image (pixel tiles, or rounds of
 // kPersistentThreads / seg_lanes(level) blocks): one workgroup each in a
 // phase launch.
-__host__ __device__ inline int phase_groups(const Dims &d, int level, int cls) {
+__host__ __device__ inline int phase_groups(const Dims &d, int level, int cls, int bppl = 1) {
     if (level == 0) return pixel_tiles(d, cls);
-    const int per = kPersistentThreads / seg_lanes(level);
+    const int per = kPersistentThreads / seg_lanes(level, bppl);
     return (class_units(d, level, cls) + per - 1) / per;
 }
 
 // Workgroups of one image in a phase launch that gives each workgroup `items`
 // work items (the last one may get fewer).
-__host__ __device__ inline int phase_launch_groups(const Dims &d, int level, int cls, int items) {
-    return (phase_groups(d, level, cls) + items - 1) / items;
+__host__ __device__ inline int phase_launch_groups(const Dims &d, int level, int cls, int items,
+                                                   int bppl = 1) {
+    return (phase_groups(d, level, cls, bppl) + items - 1) / items;
 }
 
 // Upper bound on the log entries (deltas) one workgroup produces in one work
 // item of a phase at `level`.
-__host__ __device__ inline int deltas_per_round(const Dims &d, int level) {
+__host__ __device__ inline int deltas_per_round(const Dims &d, int level, int bppl = 1) {
     if (level == 0) return 2 * kPersistentThreads;
-    const int segs = kPersistentThreads / seg_lanes(level);
+    const int segs = kPersistentThreads / seg_lanes(level, bppl);
     const int bins = (1 << (2 * level)) < d.nb ? (1 << (2 * level)) : d.nb;
     return segs * (2 * bins + 2);
 }
@@ -279,8 +305,11 @@ struct PhaseTuning {
     int items = 1;              // work items (pixel tiles, block rounds) per workgroup: 1, 2, 4
     int init_rows = kInitTH;    // rows of an initialisation tile: 8, 16, 32
     int warm_rows = kInitTH;    // rows of a warm-start tile: 8, 16, 32
+    int block_ppl = 1;          // pixels per lane at block levels 1-3: 1, 4
 };
 constexpr int kItemChoices[3] = {1, 2, 4};
+constexpr int kPplChoices[2] = {1, 4};
+__host__ __device__ inline int ppl_index(int bppl) { return bppl == 4 ? 1 : 0; }
 constexpr int kRowChoices[3] = {8, 16, 32};
 __host__ __device__ inline int item_index(int items) { return items == 4 ? 2 : items == 2 ? 1 : 0; }
 __host__ __device__ inline int row_index(int rows) { return rows == 32 ? 2 : rows == 8 ? 0 : 1; }

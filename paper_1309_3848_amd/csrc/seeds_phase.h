@@ -313,40 +313,67 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
 }
 
 // ---------------------------------------------------------------------------
-// Sparse block histogram in LDS for blocks of 16 to 64 pixels (one pixel per
-// lane; a segment of SEG lanes, all in one wavefront, owns one zeroed row h of
-// the histogram stride): every lane adds its pixel to h[j]; the lane that
-// found h[j] at 0 leads its bin, reads the bin's count h_l(j) and clears the
-// entry again. Any one lead lane per bin gives the same integer sums. A
-// wavefront's LDS operations complete in issue order, so the leader's read
-// follows every lane's addition.
-__device__ __forceinline__ void lds_bins(int j, int32_t *h, int &cnt, bool &first) {
-    cnt = 0;
-    first = false;
-    if (j == 0xFF) return;
-    first = atomicAdd(&h[j], 1) == 0;
-    if (first) {
-        cnt = __hip_atomic_load(&h[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        __hip_atomic_store(&h[j], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+// Sparse block histogram for blocks of at most 16 pixels held in registers
+// (segments of SEG lanes inside one wavefront, PPL pixels per lane; pixel tt
+// of lane i is pixel tt * SEG + i of the block): for each of the lane's bins
+// j[tt] (0xFF = no pixel), cnt = h_l(j) of its segment's block and first = no
+// lower pixel of the block has that bin. No LDS, no barrier.
+template <int SEG, int PPL>
+__device__ __forceinline__ void shuffle_bins(const int (&j)[PPL], int (&cnt)[PPL],
+                                             bool (&first)[PPL]) {
+    static_assert(SEG * PPL <= 16, "larger blocks count their bins in LDS (lds_bins)");
+    const int me = (threadIdx.x & 63) & (SEG - 1);
+#pragma unroll
+    for (int tt = 0; tt < PPL; ++tt) {
+        cnt[tt] = 0;
+        first[tt] = j[tt] != 0xFF;
+    }
+#pragma unroll
+    for (int t2 = 0; t2 < PPL; ++t2) {
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) {
+            const int v = SEG == 1 ? j[t2] : __shfl(j[t2], q, SEG);
+#pragma unroll
+            for (int tt = 0; tt < PPL; ++tt) {
+                const bool same = v == j[tt] && j[tt] != 0xFF;
+                cnt[tt] += same;
+                first[tt] = first[tt] && !(same && t2 * SEG + q < tt * SEG + me);
+            }
+        }
     }
 }
 
-// Sparse block histogram for blocks of 4 pixels (one pixel per lane,
-// segments of SEG <= 4 lanes inside one wavefront): for the lane's bin j (0xFF
-// = no pixel), cnt = h_l(j) of its segment's block and first = the lane is
-// the lowest one of its segment with that bin. No LDS, no barrier.
-template <int SEG>
-__device__ __forceinline__ void shuffle_bins(int j, int &cnt, bool &first) {
-    static_assert(SEG <= 4, "larger segments count their bins in LDS (lds_bins)");
-    const int me = (threadIdx.x & 63) & (SEG - 1);
-    cnt = 0;
-    first = j != 0xFF;
+// The same in one zeroed LDS histogram row h per segment, for blocks of 16 to
+// 64 pixels: a lane first merges its own repeated bins, then adds each of its
+// distinct bins with its multiplicity; the lane whose addition found h[j] at 0
+// leads the bin, reads h_l(j) and clears the entry again. Any one lead lane
+// per bin gives the same integer sums. A wavefront's LDS operations complete
+// in issue order, and the fence keeps the compiler from moving a read above
+// an addition, so every read follows every addition of the segment.
+template <int PPL>
+__device__ __forceinline__ void lds_bins(const int (&j)[PPL], int32_t *h, int (&cnt)[PPL],
+                                         bool (&first)[PPL]) {
+    int mult[PPL];
 #pragma unroll
-    for (int q = 0; q < SEG; ++q) {
-        const int v = __shfl(j, q, SEG);
-        const bool same = v == j && j != 0xFF;
-        cnt += same;
-        first = first && !(same && q < me);
+    for (int tt = 0; tt < PPL; ++tt) {
+        cnt[tt] = 0;
+        first[tt] = false;
+        bool repeat = false;
+        mult[tt] = 1;
+#pragma unroll
+        for (int t2 = 0; t2 < PPL; ++t2) {
+            if (t2 < tt) repeat = repeat || j[t2] == j[tt];
+            if (t2 > tt) mult[tt] += j[t2] == j[tt];
+        }
+        if (j[tt] != 0xFF && !repeat) first[tt] = atomicAdd(&h[j[tt]], mult[tt]) == 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int tt = 0; tt < PPL; ++tt) {
+        if (first[tt]) {
+            cnt[tt] = __hip_atomic_load(&h[j[tt]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_store(&h[j[tt]], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
     }
 }
 
@@ -362,6 +389,10 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
                                    DeltaTable &t, int2 *mylog) {
     constexpr int SEGS = kPT / SEG;
     constexpr int NPX = SEG * PPL;
+    // where the bins are counted (bin_count_kind): registers, an LDS row per
+    // segment, or the block's bins staged in LDS
+    constexpr int KIND = bin_count_kind(SEG, PPL);
+    constexpr int RP = KIND == 2 ? 1 : PPL;  // pixels per lane held in registers
     const Dims &d = v.d;
     int32_t *units = level_grid(v, level);
     const int s = 1 << level;
@@ -378,10 +409,8 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
     const bool exact = d.rule == SEEDS_BLOCK_EXACT;
     uint8_t *mine = sbin + seg * NPX;
     (void)mine;
-    // segments of 16 or more one-pixel lanes count their block's bins in LDS
-    constexpr bool kLdsBins = PPL == 1 && SEG >= 16;
     int32_t *seg_hist = reinterpret_cast<int32_t *>(sbin) + seg * d.hs;
-    if constexpr (kLdsBins) {
+    if constexpr (KIND == 1) {
         for (int i = lane; i < d.hs; i += SEG) seg_hist[i] = 0;
     }
     const int grp = v.grp;
@@ -396,11 +425,15 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         // The block's bins and the labels around it are independent: both
         // loads are issued before either is waited for, and blocks of up to 64
         // pixels count their bins while the labels are still in flight.
-        int j1 = 0xFF, cnt1 = 0;
-        bool first1 = false;
-        if constexpr (PPL == 1) {
-            const int x = ux * s + (lane & (s - 1)), y = uy * s + (lane >> level);
-            j1 = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
+        int jr[RP], cr[RP];
+        bool fr[RP];
+        if constexpr (KIND != 2) {
+#pragma unroll
+            for (int tt = 0; tt < PPL; ++tt) {
+                const int q = lane + tt * SEG;
+                const int x = ux * s + (q & (s - 1)), y = uy * s + (q >> level);
+                jr[tt] = (in_range && x < d.W && y < d.H) ? v.bins[(int64_t)y * d.W + x] : 0xFF;
+            }
         }
         Neighbourhood nb;
         nb.movable = false;
@@ -418,14 +451,13 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
                 ring = load_ring(units, uw, uh, ux, uy);
             }
         }
-        // Blocks of up to 64 pixels keep one bin per lane and count them with
-        // shuffles (4 pixels) or in an LDS row (16 and 64); larger blocks are
-        // staged in LDS.
-        if constexpr (PPL == 1) {
-            if constexpr (kLdsBins)
-                lds_bins(j1, seg_hist, cnt1, first1);
-            else
-                shuffle_bins<SEG>(j1, cnt1, first1);
+        // Blocks of up to 64 pixels keep their bins in registers and count
+        // them with shuffles (up to 16 pixels) or in an LDS row; larger blocks
+        // are staged in LDS.
+        if constexpr (KIND == 0) {
+            shuffle_bins<SEG, PPL>(jr, cr, fr);
+        } else if constexpr (KIND == 1) {
+            lds_bins<PPL>(jr, seg_hist, cr, fr);
         } else {
 #pragma unroll 4
             for (int tt = 0; tt < PPL; ++tt) {
@@ -439,9 +471,9 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         // pixel tt of this lane: its bin j and, if it is the first of its bin in
         // the block, the bin's count (0 otherwise)
         auto leader_bin = [&](int tt, int &j, int &cnt) {
-            if constexpr (PPL == 1) {
-                j = j1;
-                cnt = first1 ? cnt1 : 0;
+            if constexpr (KIND != 2) {
+                j = jr[tt];
+                cnt = fr[tt] ? cr[tt] : 0;
             } else {
                 const int q = lane + tt * SEG;
                 j = mine[q];
@@ -469,22 +501,29 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
                 int cs[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) cs[c] = c < nb.nc ? nb.cand[c] : k;
-                const int64_t Ak = sR[k];
-                int64_t An[4];
+                // Blocks of at most 64 pixels in images of fewer than 2^23:
+                // every term below is under 2^29 in magnitude and every sum
+                // (of one lane or of the segment) under 2^30, so they are
+                // formed in 32 bits; larger blocks use 64 bits. Only the
+                // comparisons below cross-multiply two sums.
+                using Acc = typename std::conditional<NPX <= 64, int32_t, int64_t>::type;
+                const Acc Ak = sR[k];
+                Acc An[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) An[c] = sR[cs[c]];
-                int64_t acc[4] = {0, 0, 0, 0}, acc_kl = 0;
+                const Acc mm = (Acc)m;
+                Acc acc[4] = {0, 0, 0, 0}, acc_kl = 0;
 #pragma unroll 4
                 for (int tt = 0; tt < PPL; ++tt) {
                     int j, cnt;
                     leader_bin(tt, j, cnt);
                     const int js = j == 0xFF ? 0 : j;
-                    const int64_t hk = hR[(int64_t)k * d.hs + js];
-                    int64_t hn[4];
+                    const Acc hk = hR[(int64_t)k * d.hs + js];
+                    Acc hn[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) hn[c] = hR[(int64_t)cs[c] * d.hs + js];
                     if (!cnt) continue;
-                    const int64_t hl = cnt;
+                    const Acc hl = cnt;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         if (c >= nb.nc) break;
@@ -493,22 +532,20 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
                             acc[c] += hl * (hn[c] - hk + hl);
                         } else {
                             // Prop. 1: min(h_n(j) m, h_l(j) A_n)
-                            const int64_t x1 = hn[c] * m, x2 = hl * An[c];
+                            const Acc x1 = hn[c] * mm, x2 = hl * An[c];
                             acc[c] += x1 < x2 ? x1 : x2;
                         }
                     }
                     if (!exact) {
                         // Prop. 1, k without the block: min((h_k - h_l) m, h_l (A_k - m))
-                        const int64_t x1 = (hk - hl) * m, x2 = hl * (Ak - m);
+                        const Acc x1 = (hk - hl) * mm, x2 = hl * (Ak - mm);
                         acc_kl += x1 < x2 ? x1 : x2;
                     }
                 }
-                if constexpr (PPL == 1) {
-                    // at most 64 pixels and fewer than 2^23 in the image: every
-                    // term and sum is below 2^29 and fits 32 bits
+                if constexpr (NPX <= 64) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c] = segment_sum32<SEG>((int32_t)acc[c]);
-                    acc_kl = segment_sum32<SEG>((int32_t)acc_kl);
+                    for (int c = 0; c < 4; ++c) acc[c] = segment_sum32<SEG>(acc[c]);
+                    acc_kl = segment_sum32<SEG>(acc_kl);
                 } else {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[c] = segment_sum<SEG>(acc[c]);
@@ -521,7 +558,8 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
 #pragma unroll
                 for (int c = 1; c < 4; ++c) {
                     if (c >= nb.nc) break;
-                    const bool better = exact ? acc[c] > bS : acc[c] * bA > bS * An[c];
+                    const bool better =
+                        exact ? acc[c] > bS : (int64_t)acc[c] * bA > bS * (int64_t)An[c];
                     if (better) {
                         bS = acc[c];
                         bA = An[c];
@@ -559,18 +597,29 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         } else if (in_range && pass == 1 && lane == 0) {
             v.pend[unit] = -1;
         }
-        if constexpr (PPL > 1) __syncthreads();  // LDS staging is reused next round
+        if constexpr (KIND == 2) __syncthreads();  // LDS staging is reused next round
     }
 }
 
 // BIG = false instantiates block sides up to 8 only (levels <= 4): fewer
-// registers and no scratch for the common hierarchies.
-template <bool BIG>
+// registers and no scratch for the common hierarchies. BPPL: pixels per lane
+// at levels 1-3 (seg_lanes, seg_ppl).
+template <bool BIG, int BPPL = 1>
 __device__ inline void block_phase_any(const BatchArgs &b, const ImageView &v, int level, int cls,
                                        int par, int pass, uint32_t stamp, uint8_t *sbin,
                                        DeltaTable &t, int2 *mylog) {
 #define SEEDS_BLOCK(SEG, PPL) \
     block_phase<SEG, PPL>(b, v, level, cls, par, pass, stamp, sbin, t, mylog)
+    if constexpr (BPPL == 4) {
+        if (level <= 3) {
+            switch (level) {
+                case 1: SEEDS_BLOCK(1, 4); break;
+                case 2: SEEDS_BLOCK(4, 4); break;
+                default: SEEDS_BLOCK(16, 4); break;
+            }
+            return;
+        }
+    }
     if (!BIG) {
         switch (level) {
             case 1: SEEDS_BLOCK(4, 1); break;

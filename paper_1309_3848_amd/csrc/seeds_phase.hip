@@ -21,7 +21,7 @@ __device__ __forceinline__ ImageView resolve(const BatchArgs &b, const ImageDesc
     } else {
         const int2 e = map[lg];
         const ImageDesc g = b.imgs[e.x];
-        return make_view(b, g, e.y, phase_launch_groups(g.d, level, cls, b.items));
+        return make_view(b, g, e.y, phase_launch_groups(g.d, level, cls, b.items, b.bppl));
     }
 }
 
@@ -35,7 +35,7 @@ struct PhaseWork {
 // it runs after the replay prefetch is issued so that the two overlap.
 // KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
 // workgroup from its work).
-template <bool BIG, int KINDS, bool COMPACT, typename LabT, typename Find>
+template <bool BIG, int KINDS, bool COMPACT, typename LabT, int BPPL, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups,
                                            int slot_base = 0) {
@@ -64,12 +64,12 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
     if constexpr (KINDS == 1) {
         pixel_phase<COMPACT, LabT>(b, w.v, w.cls, par, t, mylog, pl);
     } else if constexpr (KINDS == 2) {
-        block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
+        block_phase_any<BIG, BPPL>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     } else {
         if (w.level == 0)
             pixel_phase<COMPACT, LabT>(b, w.v, w.cls, par, t, mylog, pl);
         else
-            block_phase_any<BIG>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
+            block_phase_any<BIG, BPPL>(b, w.v, w.level, w.cls, par, pass, stamp, sbin, t, mylog);
     }
     if (replay_own) {
         const int n = min(pre_n, b.log_cap);
@@ -92,15 +92,18 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
 
 // PIXEL selects the pixel-level or the block-level code: each variant holds
 // only its own registers, and the block variant of the common hierarchies
-// (BIG = false) fits six wavefronts per SIMD without spilling. L16: pixel
-// labels stored as 16-bit values (pixel variants only).
+// (BIG = false) fits six wavefronts per SIMD without spilling (five with
+// four pixels per lane). L16: pixel labels stored as 16-bit values (pixel
+// variants only). BPPL: pixels per lane at block levels 1-3 (block variants
+// only).
 // Tuning (mapping only, never the moves): COMPACT for pixel phases, and
 // `remap` = 1 numbers the workgroups so that each XCD works a contiguous band.
-template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT, bool L16 = false>
-__global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
+template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT, bool L16 = false, int BPPL = 1>
+__global__ __launch_bounds__(kPT, PIXEL ? 5 : BIG ? 1 : BPPL == 1 ? 6 : 5) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
     uint32_t stamp, int replay_groups, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, typename std::conditional<L16, uint16_t, int32_t>::type>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, typename std::conditional<L16, uint16_t, int32_t>::type,
+               BPPL>(
         b,
         [&]() {
             return PhaseWork{resolve<BATCH>(b, one, map, level, cls, remap), level, cls};
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase(
 template <bool BIG, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, int32_t>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, int32_t, 1>(
         b,
         [&]() {
             const int lg = remap ? xcd_group() : (int)blockIdx.x;
@@ -168,8 +171,9 @@ __global__ __launch_bounds__(kPT) void k_descend(BatchArgs b, ImageDesc one, con
 hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *map, int max_level,
                         int level, int cls, int par, int pass, uint32_t stamp, int groups,
                         int replay_groups, const PhaseTuning &tune, hipStream_t s) {
-    const int lds = phase_lds_bytes(level, one.d.hs);
+    const int lds = phase_lds_bytes(level, one.d.hs, tune.block_ppl);
     const bool batch = b.nimg > 1;
+    const bool ppl4 = tune.block_ppl == 4;
     decltype(&k_phase<false, false, true, true>) fn;
     if (level == 0 && b.ar.lab16) {
         if (tune.pixel_compact)
@@ -183,9 +187,16 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
         else
             fn = batch ? k_phase<false, true, true, false> : k_phase<false, false, true, false>;
     } else if (max_level >= 4) {
-        fn = batch ? k_phase<true, true, false, true> : k_phase<true, false, false, true>;
+        if (ppl4)
+            fn = batch ? k_phase<true, true, false, true, false, 4> : k_phase<true, false, false, true, false, 4>;
+        else
+            fn = batch ? k_phase<true, true, false, true> : k_phase<true, false, false, true>;
     } else {
-        fn = batch ? k_phase<false, true, false, true> : k_phase<false, false, false, true>;
+        if (ppl4)
+            fn = batch ? k_phase<false, true, false, true, false, 4>
+                       : k_phase<false, false, false, true, false, 4>;
+        else
+            fn = batch ? k_phase<false, true, false, true> : k_phase<false, false, false, true>;
     }
     hipLaunchKernelGGL(fn, dim3(groups), dim3(kPT), lds, s, b, one, map, level, cls, par, pass,
                        stamp, replay_groups, tune.xcd_remap ? 1 : 0);

@@ -58,10 +58,10 @@ class seeds_server_stats(ctypes.Structure):
 class seeds_tuning(ctypes.Structure):
     _fields_ = [("pixel_compaction", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("items_per_group", ctypes.c_int32), ("init_rows", ctypes.c_int32),
-                ("warm_rows", ctypes.c_int32)]
+                ("warm_rows", ctypes.c_int32), ("block_ppl", ctypes.c_int32)]
 
 
-SEEDS_TUNE_VARIANTS = 18
+SEEDS_TUNE_VARIANTS = 21
 
 
 class seeds_quality(ctypes.Structure):
@@ -438,8 +438,10 @@ def seeds_get_tuning(ctx) -> dict:
 
 
 def seeds_set_tuning(ctx, pixel_compaction: int = 0, xcd_remap: int = 1,
-                     items_per_group: int = 1, init_rows: int = 16, warm_rows: int = 16) -> None:
-    t = seeds_tuning(pixel_compaction, xcd_remap, items_per_group, init_rows, warm_rows)
+                     items_per_group: int = 1, init_rows: int = 16, warm_rows: int = 16,
+                     block_ppl: int = 1) -> None:
+    t = seeds_tuning(pixel_compaction, xcd_remap, items_per_group, init_rows, warm_rows,
+                     block_ppl)
     _check(lib().seeds_set_tuning(ctx, ctypes.byref(t)))
 
 

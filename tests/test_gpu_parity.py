@@ -30,7 +30,10 @@ def S():
     return seeds
 
 
-MODES = {"graph": 0, "steps": 1, "persistent": 2}
+# launch modes; "graph_ppl4" is the graph mode with four pixels per lane in
+# the block phases of sides 2, 4 and 8 (tuning block_ppl = 4)
+MODES = {"graph": 0, "steps": 1, "persistent": 2, "graph_ppl4": 3}
+PPL4 = 3
 
 
 @pytest.fixture(params=list(MODES))
@@ -38,12 +41,17 @@ def mode(request):
     return MODES[request.param]
 
 
+def _set_mode(S, ctx, mode):
+    S.seeds_set_tuning(ctx, block_ppl=4 if mode == PPL4 else 1)
+    S.seeds_set_launch_mode(ctx, S.SEEDS_LAUNCH_GRAPH if mode == PPL4 else mode)
+
+
 def _gpu_run(S, img, K, L, B, I, gamma, rule, max_phases=-1, mode=0):
     import torch
     rgb = torch.from_numpy(np.ascontiguousarray(img)).cuda()
     ctx = S.seeds_init(rgb, K, S.make_params(L, B, I, gamma, rule))
     try:
-        S.seeds_set_launch_mode(ctx, mode)
+        _set_mode(S, ctx, mode)
         if max_phases < 0:
             S.seeds_refine(ctx)
         else:
@@ -208,8 +216,9 @@ def test_largest_block_sizes(S, mode):
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_alternating_launch_modes(S, rule):
-    """Phases run alternately by the persistent kernel and by per-step
-    launches: both keep the two histogram copies equal between calls."""
+    """Phases run alternately by the persistent kernel, by per-step launches
+    and by graphs with either block shape: each keeps the two histogram copies
+    equal between calls."""
     import torch
     from paper_1309_3848_amd import synth
     img = synth.voronoi_image(110, 150, 14, 8.0, seed=91)
@@ -218,8 +227,8 @@ def test_alternating_launch_modes(S, rule):
     o = oracle.Oracle(img, 36, 3, 5, 3, 1, rule)
     try:
         for i, n in enumerate([5, 4, 9, 1, 13, 2, 30, 100]):
-            S.seeds_set_launch_mode(ctx, i % 3)
-            _say(f"alternating step {i}: {n} phases mode {i % 3}")
+            _set_mode(S, ctx, i % 4)
+            _say(f"alternating step {i}: {n} phases mode {i % 4}")
             S.seeds_refine_phases(ctx, n)
             o.run(n)
             lab = torch.empty((110, 150), dtype=torch.int32)

@@ -30,11 +30,14 @@ def S():
     return seeds
 
 
-# (pixel_compaction, xcd_remap, items_per_group, init_rows): every mapping
-# combination, each with one of the three initialisation tile heights
-SETTINGS = [(c, r, it, (8, 16, 32)[(2 * c + r + it) % 3], (8, 16, 32)[(c + it) % 3])
+# (pixel_compaction, xcd_remap, items_per_group, init_rows, warm_rows,
+# block_ppl): every mapping combination, each with one of the three tile
+# heights, and every items_per_group with both block shapes
+SETTINGS = [(c, r, it, (8, 16, 32)[(2 * c + r + it) % 3], (8, 16, 32)[(c + it) % 3],
+             (1, 4)[(c + r) % 2])
             for c in (1, 0) for r in (1, 0) for it in (1, 2, 4)]
-FIELDS = ("pixel_compaction", "xcd_remap", "items_per_group", "init_rows", "warm_rows")
+FIELDS = ("pixel_compaction", "xcd_remap", "items_per_group", "init_rows", "warm_rows",
+          "block_ppl")
 
 
 @functools.lru_cache(maxsize=None)
@@ -97,7 +100,7 @@ def test_autotune_returns_a_fresh_context(S):
         chosen, ms = S.seeds_autotune(ctx, reps=2)
         assert chosen["pixel_compaction"] in (0, 1) and chosen["xcd_remap"] in (0, 1)
         assert chosen["items_per_group"] in (1, 2, 4) and chosen["init_rows"] in (8, 16, 32)
-        assert chosen["warm_rows"] in (8, 16, 32)
+        assert chosen["warm_rows"] in (8, 16, 32) and chosen["block_ppl"] in (1, 4)
         assert len(ms) == S.SEEDS_TUNE_VARIANTS and all(m > 0 for m in ms)
         assert S.seeds_get_tuning(ctx) == chosen
         assert S.seeds_level(ctx) == 2             # back at the top level
@@ -106,7 +109,8 @@ def test_autotune_returns_a_fresh_context(S):
         S.seeds_labels(ctx, lab)
         ref, _, _ = oracle.seeds(img, 200, 3, 5, 4, 1, 0)
         assert np.array_equal(lab.numpy(), ref)
-        for bad in ((2, 1, 1, 16, 16), (0, 1, 3, 16, 16), (0, 1, 1, 12, 16), (0, 1, 1, 16, 7)):
+        for bad in ((2, 1, 1, 16, 16, 1), (0, 1, 3, 16, 16, 1), (0, 1, 1, 12, 16, 1),
+                    (0, 1, 1, 16, 7, 1), (0, 1, 1, 16, 16, 2)):
             with pytest.raises(S.SeedsError):
                 S.seeds_set_tuning(ctx, *bad)
         S.seeds_set_launch_mode(ctx, S.SEEDS_LAUNCH_PERSISTENT)
