@@ -443,10 +443,14 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
         int target = -1;
         if (in_range) {
             if (pass == 2) {
+                // the recorded target and the block's label together, then the
+                // target's stamp (at a stand-in index when there is none: a
+                // load behind a branch would be waited for on its own)
                 target = v.pend[unit];
-                if (target >= 0 && v.src[target] == (int32_t)stamp) target = -1;
-                nb.movable = target >= 0;
                 nb.k = units[(int64_t)uy * uw + ux];
+                const int32_t tstamp = v.src[target >= 0 ? target : 0];
+                if (target >= 0 && tstamp == (int32_t)stamp) target = -1;
+                nb.movable = target >= 0;
             } else {
                 ring = load_ring(units, uw, uh, ux, uy);
             }
