@@ -53,5 +53,32 @@ def build(force: bool = True, verbose: bool = False) -> str:
     return LIB
 
 
+# The host-side sanitizer driver (tests/host_sanitizer_driver.cpp): every
+# library source compiled together with it into one program whose host code
+# carries AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# built as for the library), so the sanitizer runtime is linked in and nothing
+# is preloaded.
+SAN_DRIVER = os.path.join(PKG, "seeds_host_sanitized")
+SAN_SRC = os.path.join(ROOT, "tests", "host_sanitizer_driver.cpp")
+SAN_FLAGS = ("-Xarch_host -fsanitize=address,undefined -Xarch_host -fno-sanitize-recover=all "
+             "-Xarch_host -fno-omit-frame-pointer").split()
+
+
+def build_sanitized_driver(verbose: bool = False) -> str:
+    flags = [f for f in FLAGS if f not in ("-shared", "-fPIC", "-O3")]
+    tmp = SAN_DRIVER + ".tmp"
+    cmd = [HIPCC, *flags, "-O1", "-g", *SAN_FLAGS, "-I", INCLUDE, "-I", CSRC, SAN_SRC,
+           *sources(), "-o", tmp, *LIBS]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the host sanitizer driver")
+    os.replace(tmp, SAN_DRIVER)
+    return SAN_DRIVER
+
+
 if __name__ == "__main__":
     print(build(force=True, verbose=True))
+    print(build_sanitized_driver(verbose=True))
