@@ -40,7 +40,7 @@ int g_failures = 0;
     } while (0)
 
 // A pseudo-random image of smooth regions (a small linear congruential
-// generator, so the driver needs nothing but itself).
+// generator, so the program needs nothing but itself).
 std::vector<uint8_t> make_image(int H, int W, uint32_t seed) {
     uint32_t s = seed * 2654435761u + 1u;
     auto next = [&]() {

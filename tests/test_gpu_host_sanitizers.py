@@ -30,7 +30,7 @@ leak:libdrm
 def test_host_code_is_clean_under_sanitizers(tmp_path):
     exe = hipbuild.SAN_DRIVER
     if not os.path.exists(exe):
-        pytest.fail("the sanitizer driver is not built: run __graft_entry__.build()")
+        pytest.fail("the sanitizer program is not built: run __graft_entry__.build()")
     supp = tmp_path / "lsan.supp"
     supp.write_text(LSAN_SUPPRESSIONS)
     env = dict(os.environ,
