@@ -69,7 +69,7 @@ struct RefineLaunch {
 template <bool BIG, typename LabT>
 __global__ __launch_bounds__(kPT) void k_refine(RefineLaunch a) {
     extern __shared__ uint8_t sbin[];
-    __shared__ DeltaTable t;
+    __shared__ DeltaTable<> t;
     __shared__ PixelTile pl;
     __shared__ int s_prev_n;
     const BatchArgs &b = a.b;

@@ -109,31 +109,36 @@ __device__ __forceinline__ T *pick(T *const (&two)[2], int i) {
 
 // ---------------------------------------------------------------------------
 // Per-workgroup delta table in LDS (open addressing, linear probing). A
-// workgroup's phase produces at most 512-640 deltas and usually far fewer
+// workgroup's work item produces at most 512-640 deltas and usually far fewer
 // distinct keys; a 256-entry table sends the rare overflow straight to the
 // write copy and the log, and costs far less to clear and scan than a table
 // sized for the worst case (measured: 2048 entries took 11% longer per
-// refine of one 1080p image, 16% per batch).
-constexpr int kTableBits = 8;
-constexpr int kTableSize = 1 << kTableBits;
+// refine of one 1080p image, 16% per batch). The block phases of a batch
+// with four pixels per lane and several work items per workgroup use 1024
+// entries: their 512 to 1024 blocks per workgroup overflow the small table.
+constexpr int kTableBits = 8, kTableBitsMulti = 10;
 constexpr int kTableProbes = 64;
 constexpr int32_t kEmptyKey = -1;
 
+template <int BITS = kTableBits>
 struct DeltaTable {
-    int32_t key[kTableSize];
-    int32_t val[kTableSize];
+    static constexpr int kBits = BITS, kSize = 1 << BITS;
+    int32_t key[kSize];
+    int32_t val[kSize];
     int n;  // log entries written by this workgroup in this phase
 };
 
-__device__ __forceinline__ void table_clear(DeltaTable &t) {
-    for (int i = threadIdx.x; i < kTableSize; i += kPT) {
+template <typename Table>
+__device__ __forceinline__ void table_clear(Table &t) {
+    for (int i = threadIdx.x; i < Table::kSize; i += kPT) {
         t.key[i] = kEmptyKey;
         t.val[i] = 0;
     }
     if (threadIdx.x == 0) t.n = 0;
 }
 
-__device__ __forceinline__ void log_append(const BatchArgs &b, DeltaTable &t, int2 *mylog,
+template <typename Table>
+__device__ __forceinline__ void log_append(const BatchArgs &b, Table &t, int2 *mylog,
                                            int32_t idx, int32_t delta) {
     const int slot = atomicAdd(&t.n, 1);
     if (slot < b.log_cap)
@@ -144,11 +149,12 @@ __device__ __forceinline__ void log_append(const BatchArgs &b, DeltaTable &t, in
 
 // Add delta to global state index idx. A full neighbourhood in the table sends
 // the delta straight to the write copy W and the log.
-__device__ __forceinline__ void table_add(const BatchArgs &b, DeltaTable &t, int32_t *W,
+template <typename Table>
+__device__ __forceinline__ void table_add(const BatchArgs &b, Table &t, int32_t *W,
                                           int2 *mylog, int32_t idx, int32_t delta) {
-    uint32_t h = ((uint32_t)idx * 2654435761u) >> (32 - kTableBits);
+    uint32_t h = ((uint32_t)idx * 2654435761u) >> (32 - Table::kBits);
 #pragma nounroll
-    for (int p = 0; p < kTableProbes; ++p, h = (h + 1) & (kTableSize - 1)) {
+    for (int p = 0; p < kTableProbes; ++p, h = (h + 1) & (Table::kSize - 1)) {
         const int32_t prev = atomicCAS(&t.key[h], kEmptyKey, idx);
         if (prev == kEmptyKey || prev == idx) {
             atomicAdd(&t.val[h], delta);
@@ -161,9 +167,10 @@ __device__ __forceinline__ void table_add(const BatchArgs &b, DeltaTable &t, int
 
 // After the phase's moves (and a workgroup barrier): one global atomic and one
 // log entry per non-zero sum.
-__device__ __forceinline__ void table_flush(const BatchArgs &b, DeltaTable &t, int32_t *W,
+template <typename Table>
+__device__ __forceinline__ void table_flush(const BatchArgs &b, Table &t, int32_t *W,
                                             int2 *mylog) {
-    for (int i = threadIdx.x; i < kTableSize; i += kPT) {
+    for (int i = threadIdx.x; i < Table::kSize; i += kPT) {
         const int32_t k = t.key[i], v = t.val[i];
         if (k == kEmptyKey || v == 0) continue;
         atomicAdd(&W[k], v);
@@ -206,9 +213,9 @@ __device__ __forceinline__ void wave_append(PixelTile &pt, bool take, int value)
     if (take) pt.unit[base + __popcll(m & ((1ull << lane) - 1))] = value;
 }
 
-template <bool COMPACT = true, typename LabT = int32_t>
+template <bool COMPACT = true, typename LabT = int32_t, typename Table>
 __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int cls, int par,
-                                   DeltaTable &t, int2 *mylog, PixelTile &pt) {
+                                   Table &t, int2 *mylog, PixelTile &pt) {
     const Dims &d = v.d;
     LabT *const lab = label_plane<LabT>(v);
     const int cx = cls % 3, cy = cls / 3;
@@ -383,10 +390,10 @@ __device__ __forceinline__ void lds_bins(const int (&j)[PPL], int32_t *h, int (&
 //   pass 0: decide and apply at once (Prop. 1 rule; no drop rule)
 //   pass 1: exact rule, decide only: record the target and stamp the source
 //   pass 2: exact rule, apply the recorded moves whose target is no source
-template <int SEG, int PPL>
+template <int SEG, int PPL, typename Table>
 __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int level, int cls,
                                    int par, int pass, uint32_t stamp, uint8_t *sbin,
-                                   DeltaTable &t, int2 *mylog) {
+                                   Table &t, int2 *mylog) {
     constexpr int SEGS = kPT / SEG;
     constexpr int NPX = SEG * PPL;
     // where the bins are counted (bin_count_kind): registers, an LDS row per
@@ -608,10 +615,10 @@ __device__ inline void block_phase(const BatchArgs &b, const ImageView &v, int l
 // BIG = false instantiates block sides up to 8 only (levels <= 4): fewer
 // registers and no scratch for the common hierarchies. BPPL: pixels per lane
 // at levels 1-3 (seg_lanes, seg_ppl).
-template <bool BIG, int BPPL = 1>
+template <bool BIG, int BPPL = 1, typename Table>
 __device__ inline void block_phase_any(const BatchArgs &b, const ImageView &v, int level, int cls,
                                        int par, int pass, uint32_t stamp, uint8_t *sbin,
-                                       DeltaTable &t, int2 *mylog) {
+                                       Table &t, int2 *mylog) {
 #define SEEDS_BLOCK(SEG, PPL) \
     block_phase<SEG, PPL>(b, v, level, cls, par, pass, stamp, sbin, t, mylog)
     if constexpr (BPPL == 4) {

@@ -35,12 +35,12 @@ struct PhaseWork {
 // it runs after the replay prefetch is issued so that the two overlap.
 // KINDS: 1 pixel phases only, 2 block phases only, 3 both (chosen per
 // workgroup from its work).
-template <bool BIG, int KINDS, bool COMPACT, typename LabT, int BPPL, typename Find>
+template <bool BIG, int KINDS, bool COMPACT, typename LabT, int BPPL, int TBITS, typename Find>
 __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int par, int pass,
                                            uint32_t stamp, int replay_groups,
                                            int slot_base = 0) {
     extern __shared__ uint8_t sbin[];
-    __shared__ DeltaTable t;
+    __shared__ DeltaTable<TBITS> t;
     __shared__ PixelTile pl;
     table_clear(t);
     __syncthreads();
@@ -95,15 +95,17 @@ __device__ __forceinline__ void phase_body(const BatchArgs &b, Find find, int pa
 // (BIG = false) fits six wavefronts per SIMD without spilling (five with
 // four pixels per lane). L16: pixel labels stored as 16-bit values (pixel
 // variants only). BPPL: pixels per lane at block levels 1-3 (block variants
-// only).
+// only). TBITS: delta-table size (the larger one for batch block phases with
+// four pixels per lane and several work items per workgroup).
 // Tuning (mapping only, never the moves): COMPACT for pixel phases, and
 // `remap` = 1 numbers the workgroups so that each XCD works a contiguous band.
-template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT, bool L16 = false, int BPPL = 1>
+template <bool BIG, bool BATCH, bool PIXEL, bool COMPACT, bool L16 = false, int BPPL = 1,
+          int TBITS = kTableBits>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : BIG ? 1 : BPPL == 1 ? 6 : 5) void k_phase(
     BatchArgs b, ImageDesc one, const int2 *map, int level, int cls, int par, int pass,
     uint32_t stamp, int replay_groups, int remap) {
     phase_body<BIG, PIXEL ? 1 : 2, COMPACT, typename std::conditional<L16, uint16_t, int32_t>::type,
-               BPPL>(
+               BPPL, TBITS>(
         b,
         [&]() {
             return PhaseWork{resolve<BATCH>(b, one, map, level, cls, remap), level, cls};
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(kPT, PIXEL ? 5 : BIG ? 1 : BPPL == 1 ? 6 : 5) void 
 template <bool BIG, bool PIXEL, bool COMPACT>
 __global__ __launch_bounds__(kPT, PIXEL ? 5 : !BIG ? 6 : 1) void k_phase_mixed(
     BatchArgs b, TickList l, int par, int replay_groups, int slot_base, int remap) {
-    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, int32_t, 1>(
+    phase_body<BIG, PIXEL ? 1 : 2, COMPACT, int32_t, 1, kTableBits>(
         b,
         [&]() {
             const int lg = remap ? xcd_group() : (int)blockIdx.x;
@@ -174,6 +176,10 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
     const int lds = phase_lds_bytes(level, one.d.hs, tune.block_ppl);
     const bool batch = b.nimg > 1;
     const bool ppl4 = tune.block_ppl == 4;
+    // block phases of a batch with four pixels per lane and several work items
+    // per workgroup: the larger delta table (their blocks overflow the small one)
+    const bool multi = batch && ppl4 && tune.items > 1;
+    constexpr int M = kTableBitsMulti;
     decltype(&k_phase<false, false, true, true>) fn;
     if (level == 0 && b.ar.lab16) {
         if (tune.pixel_compact)
@@ -188,13 +194,16 @@ hipError_t launch_phase(const BatchArgs &b, const ImageDesc &one, const int2 *ma
             fn = batch ? k_phase<false, true, true, false> : k_phase<false, false, true, false>;
     } else if (max_level >= 4) {
         if (ppl4)
-            fn = batch ? k_phase<true, true, false, true, false, 4> : k_phase<true, false, false, true, false, 4>;
+            fn = !batch  ? k_phase<true, false, false, true, false, 4>
+                 : multi ? k_phase<true, true, false, true, false, 4, M>
+                         : k_phase<true, true, false, true, false, 4>;
         else
             fn = batch ? k_phase<true, true, false, true> : k_phase<true, false, false, true>;
     } else {
         if (ppl4)
-            fn = batch ? k_phase<false, true, false, true, false, 4>
-                       : k_phase<false, false, false, true, false, 4>;
+            fn = !batch  ? k_phase<false, false, false, true, false, 4>
+                 : multi ? k_phase<false, true, false, true, false, 4, M>
+                         : k_phase<false, true, false, true, false, 4>;
         else
             fn = batch ? k_phase<false, true, false, true> : k_phase<false, false, false, true>;
     }
