@@ -403,6 +403,23 @@ def lds_peak(S, result, stream):
                         "LDS word, conflict free (measured live)"
 
 
+def launch_floor(S, result, h, w, stream):
+    """Latency floor of the image's phase launches (project microbenchmark
+    with the same grid and launch count): empty launches, one round of window
+    loads, and two dependent rounds plus atomics, against k_phase's average
+    launch."""
+    rf = result.get("roofline") or {}
+    groups = -(-(-(-w // 3)) // 64) * -(-(-(-h // 3)) // 4)  # class-0 pixel tiles of 64 x 4
+    launches = result.get("launches_per_image") or 144
+    us = S.seeds_launch_floor(groups, launches, stream)
+    rf["launch_floor_us"] = {"empty": round(us[0], 3), "one_round_trip": round(us[1], 3),
+                             "two_round_trips": round(us[2], 3), "groups": groups,
+                             "launches": launches,
+                             "source": "seeds_launch_floor (measured live)"}
+    if rf.get("avg_launch_us"):
+        rf["frac_of_launch_floor"] = round(us[2] / rf["avg_launch_us"], 3)
+
+
 # ---- batch (C3) -------------------------------------------------------------------
 
 def run_batch(args) -> dict:
@@ -1105,6 +1122,7 @@ def main() -> int:
                        TRAFFIC_FILE if args.workload == "single1080p" else None,
                        LDS_FILE if args.workload == "single1080p" else None)
         lds_peak(S, r, stream)
+        launch_floor(S, r, img.shape[0], img.shape[1], stream)
         print(json.dumps(_line(r)), flush=True)
         return 0
     if args.workload != "all":
@@ -1116,6 +1134,7 @@ def main() -> int:
     head = run_single(args, synth.single_1080p(), K, LEVELS, c2_name, steps, warmup, TRAFFIC_FILE,
                       LDS_FILE)
     lds_peak(S, head, stream)
+    launch_floor(S, head, 1080, 1920, stream)
     print(f"[bench] 1080p done in {time.perf_counter() - t_all:.1f} s", file=sys.stderr, flush=True)
     skip = set(filter(None, args.skip.split(",")))
     nested = {}

@@ -480,6 +480,18 @@ seeds_status seeds_segment_noalloc(const uint8_t *rgb, int32_t H, int32_t W,
  * little device memory and waits for the stream.                          */
 seeds_status seeds_lds_atomic_rate(double *ginst_per_s, void *hip_stream);
 
+/* Latency floor of a phase launch on the current device: chains of `launches`
+ * launches (a HIP graph on a private stream, best of three replays after a
+ * warm-up) with the shape of one phase launch, `groups` workgroups of 256
+ * lanes, doing us[0] nothing, us[1] one round of coalesced loads (fourteen
+ * 2-byte loads per lane, 7 KB per workgroup, like a pixel tile's window),
+ * us[2] that round, then five dependent loads per lane from a 512 KB table
+ * (the histogram cells of a decision) and a few global atomics per workgroup.
+ * us[0..2] receive microseconds per launch. groups in [1,65536], launches in
+ * [1,4096]. Allocates device memory for the call, waits for hip_stream first
+ * and for its own stream at the end.                                        */
+seeds_status seeds_launch_floor(int32_t groups, int32_t launches, double *us, void *hip_stream);
+
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */
 seeds_status seeds_destroy(seeds_ctx *ctx);

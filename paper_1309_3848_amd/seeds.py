@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
             "seeds_snapshot": ([P, P, I64, P], S),
             "seeds_restore": ([P, P, I64, P], S),
             "seeds_lds_atomic_rate": ([ctypes.POINTER(ctypes.c_double), P], S),
+            "seeds_launch_floor": ([I32, I32, ctypes.POINTER(ctypes.c_double), P], S),
             "seeds_debug_inject_fault": ([I32, I32], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
@@ -475,6 +476,15 @@ def seeds_lds_atomic_rate(stream=None) -> float:
     r = ctypes.c_double()
     _check(lib().seeds_lds_atomic_rate(ctypes.byref(r), _stream(stream)))
     return r.value
+
+
+def seeds_launch_floor(groups: int, launches: int = 144, stream=None) -> list:
+    """Microseconds per launch of graph-captured launches of `groups`
+    workgroups doing nothing, one round of window loads, and two dependent
+    rounds plus atomics (the latency floor of a phase launch)."""
+    us = (ctypes.c_double * 3)()
+    _check(lib().seeds_launch_floor(groups, launches, us, _stream(stream)))
+    return [us[0], us[1], us[2]]
 
 
 SEEDS_FAULT_ALLOC = 0

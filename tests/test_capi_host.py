@@ -229,6 +229,15 @@ def test_server_without_a_device_reports_device_error(S):
     assert not srv.value
 
 
+def test_launch_floor_argument_checks(S):
+    L = S.lib()
+    us = (ctypes.c_double * 3)()
+    assert L.seeds_launch_floor(900, 144, None, None) == S.SEEDS_E_INVAL
+    for groups, launches in ((0, 144), (65537, 144), (900, 0), (900, 4097)):
+        assert L.seeds_launch_floor(groups, launches, us, None) == S.SEEDS_E_INVAL
+    assert b"outside" in S.lib().seeds_last_error()
+
+
 def test_tuning_argument_checks(S):
     L = S.lib()
     t = S.seeds_tuning(1, 1)
