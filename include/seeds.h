@@ -221,7 +221,9 @@ seeds_status seeds_set_launch_mode(seeds_ctx *ctx, int32_t mode);
  *                     phases of block sides 2, 4 and 8 (1: 4, 16 and 64
  *                     lanes per block; 4: 1, 4 and 16 lanes, so a wavefront
  *                     decides four times as many blocks at once). Larger
- *                     blocks always take 64 lanes.
+ *                     blocks always take 64 lanes. In a batch with
+ *                     block_ppl 4 and items_per_group > 1, the block phases'
+ *                     per-workgroup delta tables are four times larger.
  * Default: pixel_compaction 0, xcd_remap 1, items_per_group 1, init_rows 16,
  * warm_rows 16, block_ppl 1.                                                */
 typedef struct {
