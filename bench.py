@@ -403,14 +403,14 @@ def lds_peak(S, result, stream):
                         "LDS word, conflict free (measured live)"
 
 
-def launch_floor(S, result, h, w, stream):
+def launch_floor(S, result, h, w, stream, launches=None):
     """Latency floor of the image's phase launches (project microbenchmark
     with the same grid and launch count): empty launches, one round of window
     loads, and two dependent rounds plus atomics, against k_phase's average
     launch."""
     rf = result.get("roofline") or {}
     groups = -(-(-(-w // 3)) // 64) * -(-(-(-h // 3)) // 4)  # class-0 pixel tiles of 64 x 4
-    launches = result.get("launches_per_image") or 144
+    launches = launches or result.get("launches_per_image") or 144
     us = S.seeds_launch_floor(groups, launches, stream)
     rf["launch_floor_us"] = {"empty": round(us[0], 3), "one_round_trip": round(us[1], 3),
                              "two_round_trips": round(us[2], 3), "groups": groups,
@@ -722,6 +722,7 @@ def run_stream(args) -> dict:
                                     f"then warm starts), {omp_s:.1f} s"},
             "host": host_info(), "paper_context": PAPER_CONTEXT}
         result["bitexact_vs_oracle"] = same
+    launch_floor(S, result, SH, SW, stream, launches=ITERS * 9)  # a warm frame's pixel phases
     return result
 
 
