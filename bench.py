@@ -403,13 +403,18 @@ def lds_peak(S, result, stream):
                         "LDS word, conflict free (measured live)"
 
 
-def launch_floor(S, result, h, w, stream, launches=None):
+def pixel_tiles(h, w):
+    """Workgroups of a class-0 pixel-level launch: tiles of 64 x 4 pixels of one class."""
+    return -(-(-(-w // 3)) // 64) * -(-(-(-h // 3)) // 4)
+
+
+def launch_floor(S, result, h, w, stream, launches=None, groups=None):
     """Latency floor of the image's phase launches (project microbenchmark
     with the same grid and launch count): empty launches, one round of window
     loads, and two dependent rounds plus atomics, against k_phase's average
-    launch."""
+    launch. A batch passes the sum of its images' tiles as `groups`."""
     rf = result.get("roofline") or {}
-    groups = -(-(-(-w // 3)) // 64) * -(-(-(-h // 3)) // 4)  # class-0 pixel tiles of 64 x 4
+    groups = groups or pixel_tiles(h, w)
     launches = launches or result.get("launches_per_image") or 144
     us = S.seeds_launch_floor(groups, launches, stream)
     rf["launch_floor_us"] = {"empty": round(us[0], 3), "one_round_trip": round(us[1], 3),
@@ -418,6 +423,11 @@ def launch_floor(S, result, h, w, stream, launches=None):
                              "source": "seeds_launch_floor (measured live)"}
     if rf.get("avg_launch_us"):
         rf["frac_of_launch_floor"] = round(us[2] / rf["avg_launch_us"], 3)
+        if us[2] > rf["avg_launch_us"]:
+            rf["launch_floor_us"]["note"] = (
+                "the two-round skeleton loads five table cells in every lane and a 7 KB window "
+                "per workgroup; here it takes longer than the phase, so it is bound by its own "
+                "loads, not by latency, and only the empty launch bounds the phase")
 
 
 # ---- batch (C3) -------------------------------------------------------------------
@@ -542,6 +552,8 @@ def run_batch(args) -> dict:
                              prof, avg_us, None),
     }
     result["roofline"]["traffic_note"] = "not measured: see the batch profile notes"
+    launch_floor(S, result, 0, 0, stream, launches=launches,
+                 groups=min(sum(pixel_tiles(s["H"], s["W"]) for s in specs), 65536))
     if not args.no_cpu_baseline:
         import oracle
         order = np.argsort([s["H"] * s["W"] for s in specs])
