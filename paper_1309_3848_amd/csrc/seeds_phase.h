@@ -311,8 +311,8 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
                 const int u = pt.unit[threadIdx.x];
                 const int ui = (u & 0xFF) % kPixTX, uj = (u & 0xFF) / kPixTX, uj_bin = u >> 8;
                 const int px = x0 + 3 * ui, py = y0 + 3 * uj;
-                const PixelMove mv =
-                    pixel_decision(d, pt.lab + 3 * uj * kWinW + 3 * ui, uj_bin, hR, px, py);
+                const PixelMove mv = pixel_decision<false>(d, pt.lab + 3 * uj * kWinW + 3 * ui,
+                                                           uj_bin, hR, px, py);
                 if (mv.n >= 0) apply(px, py, uj_bin, mv);
             }
         }
