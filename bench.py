@@ -22,7 +22,9 @@ this run with its own step counts, roofline and CPU baseline:
               path under the same arrivals; latency from arrival to labels in
               host memory.
 `--workload NAME` runs one of them alone (or `quality`: the metrics of
-Sec. 6.1 for the grid, pixel-only updates and SEEDS) and prints its line.
+Sec. 6.1 for the grid, pixel-only updates and SEEDS; `single4k`: the 4K
+stream's first frame as a single image refined from scratch, K 5000, a size
+at which the block phases can be profiled) and prints its line.
 
 Roofline. `roofline.achieved` is the algorithmic bytes of one k_phase launch
 over the launch's average duration. Algorithmic bytes follow the byte model
@@ -1065,8 +1067,8 @@ def _line(result: dict) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["all", "single1080p", "c1", "batch64", "stream4k",
-                                           "quality", "serve"], default="all",
+    ap.add_argument("--workload", choices=["all", "single1080p", "c1", "single4k", "batch64",
+                                           "stream4k", "quality", "serve"], default="all",
                     help="all (default): the 1080p headline with the other workloads nested")
     ap.add_argument("--steps", type=int, default=None, help="headline steps (default 200)")
     ap.add_argument("--warmup", type=int, default=None, help="headline warm-up (default 20)")
@@ -1129,6 +1131,11 @@ def main() -> int:
         return 0
     single = {"single1080p": ("c2", synth.single_1080p(), K, LEVELS, c2_name),
               "c1": ("c1", synth.single_481x321(), 200, 3, c1_name)}
+    if args.workload == "single4k":  # the 4K stream's first frame, refined from scratch
+        single["single4k"] = ("4k", synth.StreamScene(H=2160, W=3840, regions=1500, frames=1).frame(0),
+                              5000, LEVELS, "single 3840x2160 RGB u8 image: frame 0 of the 4K stream "
+                              "scene (1500 Voronoi regions, noise sigma 8, seeds 4 / 4000); K=5000, "
+                              "4 levels, 5 bins/channel, 4 sweeps/level, gamma 1, Prop. 1 block rule")
     if args.workload in single:
         _, img, k, lv, name = single[args.workload]
         r = run_single(args, img, k, lv, name, steps, warmup,
