@@ -161,6 +161,35 @@ def test_tiles_meeting_many_superpixels(S, H, W, K, L, mode):
     _compare(S, img, K, L, B=5, I=2, gamma=1, mode=mode)
 
 
+def _junction_pixels(lab):
+    """Pixels 2 or more cells inside the image whose four edge neighbours
+    carry three labels other than their own."""
+    H, W = lab.shape
+    c = lab[2:H - 2, 2:W - 2]
+    nbrs = [lab[1:H - 3, 2:W - 2], lab[2:H - 2, 3:W - 1], lab[3:H - 1, 2:W - 2], lab[2:H - 2, 1:W - 3]]
+    count = np.zeros(c.shape, int)
+    for i, n in enumerate(nbrs):
+        new = n != c
+        for m in nbrs[:i]:
+            new &= n != m
+        count += new
+    return int((count >= 3).sum())
+
+
+@pytest.mark.parametrize("gamma", [2, 7])
+def test_pixel_decisions_at_junctions(S, gamma, mode):
+    """Superpixels of about 3x3 pixels on a 96 x 640 image: the pixel sweeps
+    decide many pixels with two and three candidate labels, in wavefronts whose
+    pixels are all 2 or more cells inside the image (constant boundary-term
+    weights: the image is wider than a wavefront's 190-pixel span) and in
+    wavefronts touching the border (computed weights)."""
+    from paper_1309_3848_amd import synth
+    assert oracle.grid(96, 640, 6800, 2) is not None
+    img = synth.voronoi_image(96, 640, 60, 14.0, seed=77 + gamma)
+    lab = _compare(S, img, K=6800, L=2, B=4, I=3, gamma=gamma, mode=mode)
+    assert _junction_pixels(lab) > 1000
+
+
 @pytest.mark.parametrize("compaction", [1, 0])
 @pytest.mark.parametrize("H,W", [
     (11, 189), (12, 190), (13, 191), (14, 192), (15, 193), (24, 194), (25, 195), (26, 196),
