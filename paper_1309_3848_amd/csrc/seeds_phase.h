@@ -260,13 +260,23 @@ __device__ inline void pixel_phase(const BatchArgs &b, const ImageView &v, int c
             j = v.bins[(int64_t)min(y, d.H - 1) * d.W + min(x, d.W - 1)];
             const int xc = min(max(xx, 0), d.W - 1);
             if (wide) {
+                if (y0 >= 2 && y0 - 2 + kWinH <= d.H) {
+                    // every window row lies in the image: rows from one base
+                    const LabT *base = lab + (int64_t)(y0 - 2) * d.W + xc;
 #pragma unroll
-                for (int r = 0; r < kWinH; ++r)
-                    cell[r] = lab[(int64_t)min(max(y0 - 2 + r, 0), d.H - 1) * d.W + xc];
+                    for (int r = 0; r < kWinH; ++r) cell[r] = base[(int64_t)r * d.W];
 #pragma unroll
-                for (int r = 0; r < kWinH; ++r) {
-                    const int yy = y0 - 2 + r;
-                    if (!(in_x && yy >= 0 && yy < d.H)) cell[r] = -1;
+                    for (int r = 0; r < kWinH; ++r)
+                        if (!in_x) cell[r] = -1;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < kWinH; ++r)
+                        cell[r] = lab[(int64_t)min(max(y0 - 2 + r, 0), d.H - 1) * d.W + xc];
+#pragma unroll
+                    for (int r = 0; r < kWinH; ++r) {
+                        const int yy = y0 - 2 + r;
+                        if (!(in_x && yy >= 0 && yy < d.H)) cell[r] = -1;
+                    }
                 }
             } else {
                 const int yy = y0 - 2 + min(wr, kWinH - 1);
