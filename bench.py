@@ -24,7 +24,9 @@ this run with its own step counts, roofline and CPU baseline:
 `--workload NAME` runs one of them alone (or `quality`: the metrics of
 Sec. 6.1 for the grid, pixel-only updates and SEEDS; `single4k`: the 4K
 stream's first frame as a single image refined from scratch, K 5000, a size
-at which the block phases can be profiled) and prints its line.
+at which the block phases can be profiled; `traffic_probe`: the 64 MiB
+calibration copy and the library's traffic probes, kernels of known traffic
+for reading profiler byte counters) and prints its line.
 
 Roofline. `roofline.achieved` is the algorithmic bytes of one k_phase launch
 over the launch's average duration. Algorithmic bytes follow the byte model
@@ -1064,11 +1066,30 @@ def _line(result: dict) -> dict:
     return out
 
 
+def run_traffic_probe(S, torch, stream, lines=1 << 19):
+    """Kernels of known traffic for reading profiler byte counters: the 64 MiB
+    device copy the phase profiles are scaled by, then the library's three
+    traffic probes over 64 MiB of 128-byte lines (a coalesced read, one
+    scattered 4-byte read per line, one scattered 4-byte atomic per line).
+    Run under rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE."""
+    src = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    us = S.seeds_traffic_probe(lines, stream)
+    return {"workload": "traffic probes", "copy_bytes": 64 << 20, "lines": lines,
+            "line_bytes": 128, "buffer_bytes": lines * 128,
+            "us": {"k_probe_stream": round(us[0], 2), "k_probe_scatter": round(us[1], 2),
+                   "k_probe_atomic": round(us[2], 2)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["all", "single1080p", "c1", "single4k", "batch64",
-                                           "stream4k", "quality", "serve"], default="all",
+                                           "stream4k", "quality", "serve", "traffic_probe"],
+                    default="all",
                     help="all (default): the 1080p headline with the other workloads nested")
     ap.add_argument("--steps", type=int, default=None, help="headline steps (default 200)")
     ap.add_argument("--warmup", type=int, default=None, help="headline warm-up (default 20)")
@@ -1125,6 +1146,9 @@ def main() -> int:
                "(seed 1); K=200 (204 on the grid), 3 levels, 5 bins/channel, 4 sweeps/level, "
                "gamma 1, Prop. 1 block rule")
     stream = torch.cuda.current_stream()
+    if args.workload == "traffic_probe":
+        print(json.dumps(run_traffic_probe(S, torch, stream)), flush=True)
+        return 0
     if args.workload == "quality":
         args.steps, args.warmup = (20 if args.steps is None else args.steps), warmup
         print(json.dumps(_line(run_quality(args))), flush=True)

@@ -494,6 +494,24 @@ seeds_status seeds_lds_atomic_rate(double *ginst_per_s, void *hip_stream);
  * and for its own stream at the end.                                        */
 seeds_status seeds_launch_floor(int32_t groups, int32_t launches, double *us, void *hip_stream);
 
+/* Traffic probes: three kernels of exactly known memory traffic, for scaling
+ * a profiler's byte counters (rocprofv3 FETCH_SIZE, WRITE_SIZE) to the access
+ * kinds of the refinement kernels, which mostly read scattered 4-byte words
+ * and add to them atomically. A buffer of `lines` 128-byte lines (a power of
+ * two in [2^10, 2^22]), every int32 word 0x01010101, is touched line by line,
+ * each line exactly once per kernel, in this stream order:
+ *   k_probe_stream   reads the whole buffer with coalesced 16-byte loads;
+ *   k_probe_scatter  reads one 4-byte word per line, the lines in a permuted
+ *                    order (the 64 lanes of a wavefront hit 64 distinct lines);
+ *   k_probe_atomic   adds 1 to one 4-byte word per line, same order.
+ * us[0..2] receive each kernel's event-timed duration in microseconds (one
+ * launch each, after an untimed one-workgroup launch of each kernel; under a
+ * profiler these are dispatches 4, 5 and 6 of the call, its own durations
+ * are the ones to read). Allocates the buffer for the call, waits for hip_stream,
+ * and checks what each kernel summed (SEEDS_E_DEVICE on a mismatch);
+ * SEEDS_E_INVAL for a NULL us or an invalid `lines`.                        */
+seeds_status seeds_traffic_probe(int64_t lines, double *us, void *hip_stream);
+
 /* Release the context and its device memory (after synchronising the stream
  * it last used). NULL is accepted.                                            */
 seeds_status seeds_destroy(seeds_ctx *ctx);

@@ -5,6 +5,7 @@
 // nothing conflicts; the rate is wavefront instructions per second.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "seeds.h"
@@ -67,10 +68,137 @@ __global__ __launch_bounds__(kMbThreads) void k_floor_two(const uint16_t *plane,
     if ((sum & 63) == 0) atomicAdd(&out[(sum + acc) & (kFloorTable - 1)], 1);
 }
 
+// Traffic probes: three kernels whose memory traffic is known exactly, for
+// reading a profiler's byte counters on the access kinds of the refinement
+// kernels. The buffer holds `lines` 128-byte lines of int32 (a power of two);
+// every probe touches each line exactly once:
+//   stream  reads the whole buffer with coalesced 16-byte loads;
+//   scatter reads one 4-byte word per line, lines visited in a permuted
+//           order (thread i takes line (i * odd) mod lines, a bijection), so
+//           the 64 lanes of a wavefront hit 64 lines far apart;
+//   atomic  adds 1 to one word per line in the same permuted order.
+// Each workgroup sums what it read (the atomics: the old values) and stores
+// the sum to its own word of `part` (plain stores to distinct words, so no
+// same-address atomics queue up behind the probe); the host adds them up.
+constexpr int kLineWords = 32;
+constexpr uint32_t kProbeOdd = 0x9E3779B1u;
+
+__device__ __forceinline__ void probe_sum(long long v, unsigned long long *part) {
+    __shared__ long long waves[kMbThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) waves[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+#pragma unroll
+        for (int w = 0; w < kMbThreads / 64; ++w) t += waves[w];
+        part[blockIdx.x] = (unsigned long long)t;
+    }
+}
+
+__global__ __launch_bounds__(kMbThreads) void k_probe_stream(const int4 *buf, int64_t n4,
+                                                             unsigned long long *part) {
+    long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kMbThreads + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * kMbThreads) {
+        const int4 q = buf[i];
+        acc += (long long)q.x + q.y + q.z + q.w;
+    }
+    probe_sum(acc, part);
+}
+
+// grid: exactly lines / 256 workgroups (lines is a power of two >= 1024)
+__global__ __launch_bounds__(kMbThreads) void k_probe_scatter(const int32_t *buf, uint32_t mask,
+                                                              unsigned long long *part) {
+    const uint32_t line = ((blockIdx.x * kMbThreads + threadIdx.x) * kProbeOdd) & mask;
+    probe_sum(buf[(size_t)line * kLineWords], part);
+}
+
+__global__ __launch_bounds__(kMbThreads) void k_probe_atomic(int32_t *buf, uint32_t mask,
+                                                             unsigned long long *part) {
+    const uint32_t line = ((blockIdx.x * kMbThreads + threadIdx.x) * kProbeOdd) & mask;
+    probe_sum(atomicAdd(&buf[(size_t)line * kLineWords], 1), part);
+}
+
 }  // namespace
 }  // namespace seeds
 
 using namespace seeds;
+
+extern "C" seeds_status seeds_traffic_probe(int64_t lines, double *us, void *hip_stream) {
+    if (!us) return set_error(SEEDS_E_INVAL, "output is NULL");
+    if (lines < 1024 || lines > (int64_t)1 << 22 || (lines & (lines - 1)))
+        return set_error(SEEDS_E_INVAL, "lines %lld is not a power of two in [2^10, 2^22]",
+                         (long long)lines);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t bytes = (size_t)lines * kLineWords * sizeof(int32_t);
+    const int groups = (int)(lines / kMbThreads);
+    const int sgroups = std::min(groups * 2, 4096);  // the streaming read's grid
+    const int nparts = sgroups + 2 * groups;         // one word per workgroup of each probe
+    int32_t *buf = nullptr;
+    unsigned long long *part = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = hipMalloc(&buf, bytes);
+    if (e == hipSuccess) e = hipMalloc(&part, nparts * sizeof(unsigned long long));
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    // every word 0x01010101
+    if (e == hipSuccess) e = hipMemsetAsync(buf, 1, bytes, s);
+    const uint32_t mask = (uint32_t)(lines - 1);
+    // untimed warm-up: one workgroup of each probe, so the timed launches do
+    // not include loading the kernels (its atomics add 1 to the probed word of
+    // the 256 lines of workgroup 0, which every timed probe then reads)
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_probe_stream, dim3(1), dim3(kMbThreads), 0, s, (const int4 *)buf,
+                           (int64_t)kMbThreads, part);
+        hipLaunchKernelGGL(k_probe_scatter, dim3(1), dim3(kMbThreads), 0, s, buf, mask, part);
+        hipLaunchKernelGGL(k_probe_atomic, dim3(1), dim3(kMbThreads), 0, s, buf, mask, part);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_probe_stream, dim3(sgroups), dim3(kMbThreads), 0, s,
+                           (const int4 *)buf, (int64_t)(bytes / sizeof(int4)), part);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_probe_scatter, dim3(groups), dim3(kMbThreads), 0, s, buf, mask,
+                           part + sgroups);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_probe_atomic, dim3(groups), dim3(kMbThreads), 0, s, buf, mask,
+                           part + sgroups + groups);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+    std::vector<unsigned long long> h(nparts, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), part, nparts * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        us[i] = ms * 1e3;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (buf) (void)hipFree(buf);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess) return set_error(SEEDS_E_DEVICE, "traffic probe: %s", hipGetErrorString(e));
+    unsigned long long got[3] = {0, 0, 0};
+    for (int i = 0; i < nparts; ++i) got[i < sgroups ? 0 : i < sgroups + groups ? 1 : 2] += h[i];
+    const unsigned long long word = 0x01010101ull, n = (unsigned long long)lines;
+    // the warm-up's atomics added 1 to one word of each of 256 lines
+    if (got[0] != n * kLineWords * word + kMbThreads || got[1] != n * word + kMbThreads ||
+        got[2] != n * word + kMbThreads)
+        return set_error(SEEDS_E_DEVICE, "traffic probe: sums %llu %llu %llu", got[0], got[1],
+                         got[2]);
+    return SEEDS_OK;
+}
 
 extern "C" seeds_status seeds_launch_floor(int32_t groups, int32_t launches, double *us,
                                            void *hip_stream) {

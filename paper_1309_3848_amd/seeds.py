@@ -132,6 +132,7 @@ def lib() -> ctypes.CDLL:
             "seeds_restore": ([P, P, I64, P], S),
             "seeds_lds_atomic_rate": ([ctypes.POINTER(ctypes.c_double), P], S),
             "seeds_launch_floor": ([I32, I32, ctypes.POINTER(ctypes.c_double), P], S),
+            "seeds_traffic_probe": ([I64, ctypes.POINTER(ctypes.c_double), P], S),
             "seeds_debug_inject_fault": ([I32, I32], S),
             "seeds_destroy": ([P], S),
             "seeds_last_error": ([], ctypes.c_char_p),
@@ -484,6 +485,15 @@ def seeds_launch_floor(groups: int, launches: int = 144, stream=None) -> list:
     rounds plus atomics (the latency floor of a phase launch)."""
     us = (ctypes.c_double * 3)()
     _check(lib().seeds_launch_floor(groups, launches, us, _stream(stream)))
+    return [us[0], us[1], us[2]]
+
+
+def seeds_traffic_probe(lines: int = 1 << 19, stream=None) -> list:
+    """Event-timed microseconds of the three traffic probes over `lines`
+    128-byte lines: a coalesced read of the buffer, one scattered 4-byte read
+    per line, one scattered 4-byte atomic add per line."""
+    us = (ctypes.c_double * 3)()
+    _check(lib().seeds_traffic_probe(lines, us, _stream(stream)))
     return [us[0], us[1], us[2]]
 
 

@@ -238,6 +238,15 @@ def test_launch_floor_argument_checks(S):
     assert b"outside" in S.lib().seeds_last_error()
 
 
+def test_traffic_probe_argument_checks(S):
+    L = S.lib()
+    us = (ctypes.c_double * 3)()
+    assert L.seeds_traffic_probe(1 << 19, None, None) == S.SEEDS_E_INVAL
+    for lines in (0, 512, 1000, 3 << 18, (1 << 22) + 1, 1 << 23, -1024):
+        assert L.seeds_traffic_probe(lines, us, None) == S.SEEDS_E_INVAL
+    assert b"power of two" in S.lib().seeds_last_error()
+
+
 def test_tuning_argument_checks(S):
     L = S.lib()
     t = S.seeds_tuning(1, 1)

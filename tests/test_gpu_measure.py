@@ -1,6 +1,7 @@
 """The measurement hooks run and give plausible figures: the LDS-atomic rate
-(the secondary roof) and the latency floor of a phase launch (empty launches,
-one round of window loads, two dependent rounds with atomics)."""
+(the secondary roof), the latency floor of a phase launch (empty launches,
+one round of window loads, two dependent rounds with atomics) and the traffic
+probes (whose sums the library checks itself)."""
 import sys
 
 import pytest
@@ -39,3 +40,15 @@ def test_launch_floor(S, groups, launches):
     # launch (over a few launches the graph's own start dominates)
     if launches >= 100:
         assert two > empty
+
+
+@pytest.mark.parametrize("lines", [1 << 10, 1 << 19])
+def test_traffic_probe(S, lines):
+    _say(f"traffic probe lines {lines}")
+    us = S.seeds_traffic_probe(lines)
+    assert all(0.0 < t < 1e6 for t in us)
+    if lines >= 1 << 19:
+        # 64 MiB read at more than 8 TB/s would be faster than HBM allows
+        # (the buffer was just written, but a 64 MiB read still cannot finish
+        # in under 2 us)
+        assert us[0] > 2.0
