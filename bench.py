@@ -464,8 +464,7 @@ def run_batch(args) -> dict:
     def step():
         S.seeds_batch_reinit(ctx, rgbs, stream)
         S.seeds_refine(ctx, stream)
-        for i in range(len(specs)):
-            S.seeds_batch_labels(ctx, i, outs[i], stream)
+        S.seeds_batch_labels_all(ctx, outs, stream)
 
     for _ in range(warmup):
         step()

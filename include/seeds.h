@@ -338,6 +338,17 @@ seeds_status seeds_batch_labels(const seeds_ctx *ctx, int32_t image, int32_t *ou
 seeds_status seeds_batch_histograms(const seeds_ctx *ctx, int32_t image, int32_t *hist,
                                     int32_t *size, int32_t out_is_host, void *hip_stream);
 int32_t seeds_batch_num_superpixels(const seeds_ctx *ctx, int32_t image);
+
+/* seeds_batch_labels to device memory for every image of the context at
+ * once: outs is a host array of seeds_batch_count(ctx) device pointers,
+ * outs[i] receiving image i's H_i x W_i int32 labels (row-major), written in
+ * stream order without waiting. Images whose labels are 16-bit pixel labels
+ * are converted together, up to 64 per launch; any other image takes its own
+ * copy. SEEDS_E_INVAL (before any device work) for a NULL ctx, outs or
+ * outs[i]; SEEDS_E_DEVICE if a launch fails (the context is then
+ * poisoned, as for seeds_batch_labels).                                      */
+seeds_status seeds_batch_labels_all(const seeds_ctx *ctx, int32_t *const *outs,
+                                    void *hip_stream);
 seeds_status seeds_batch_energy(const seeds_ctx *ctx, int32_t image, int64_t *h_energy,
                                 int64_t *g_energy, void *hip_stream);
 

@@ -22,6 +22,7 @@
 
 #include "seeds.h"
 #include "seeds_internal.h"
+#include "seeds_readback.h"
 #include "seeds_trace.h"
 
 using namespace seeds;
@@ -1191,6 +1192,40 @@ seeds_status seeds_batch_labels(const seeds_ctx *cctx, int32_t image, int32_t *o
     if (st != SEEDS_OK) return st;
     if (!out) return fail(SEEDS_E_INVAL, "out is NULL");
     return labels_of(ctx, image, out, out_is_host, (hipStream_t)hip_stream);
+}
+
+seeds_status seeds_batch_labels_all(const seeds_ctx *cctx, int32_t *const *outs,
+                                    void *hip_stream) {
+    seeds_ctx *ctx = const_cast<seeds_ctx *>(cctx);
+    seeds_status st = check_image(ctx, 0);
+    if (st != SEEDS_OK) return st;
+    if (!outs) return fail(SEEDS_E_INVAL, "outs is NULL");
+    for (int i = 0; i < ctx->nimg; ++i)
+        if (!outs[i]) return fail(SEEDS_E_INVAL, "outs[%d] is NULL", i);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // images at pixel level with a 16-bit plane: widened together, up to
+    // kReadbackMax per launch; any other image through its own copy
+    ReadbackList l;
+    l.count = 0;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < ctx->nimg && e == hipSuccess; ++i) {
+        const ImageDesc &g = ctx->imgs[i];
+        if (!ctx->ar.lab16 || image_level(ctx, i) > 0) {
+            st = labels_of(ctx, i, outs[i], 0, s);
+            if (st != SEEDS_OK) return st;
+            continue;
+        }
+        l.src[l.count] = ctx->ar.lab16 + g.lab;
+        l.dst[l.count] = outs[i];
+        l.n[l.count] = (int64_t)g.d.H * g.d.W;
+        if (++l.count == kReadbackMax) {
+            e = launch_widen_list(l, s);
+            l.count = 0;
+        }
+    }
+    if (e == hipSuccess) e = launch_widen_list(l, s);
+    if (e != hipSuccess) return device_error(ctx, e, "labels copy");
+    return SEEDS_OK;
 }
 
 int32_t seeds_num_superpixels(const seeds_ctx *ctx) { return seeds_batch_num_superpixels(ctx, 0); }

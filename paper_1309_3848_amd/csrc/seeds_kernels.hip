@@ -3,6 +3,7 @@
 // seeds_phase.hip (one launch per phase) and seeds_persistent.hip (one
 // launch per refinement).
 #include "seeds_device.h"
+#include "seeds_readback.h"
 
 namespace seeds {
 namespace {
@@ -376,6 +377,17 @@ __global__ __launch_bounds__(kThreads) void k_widen(int32_t *__restrict__ dst,
         dst[i] = (int32_t)src[i];
 }
 
+// The same for every image of a readback list in one launch: workgroup row
+// blockIdx.y serves image blockIdx.y, its gridDim.x workgroups stride over it.
+__global__ __launch_bounds__(kThreads) void k_widen_list(ReadbackList l) {
+    const int i = blockIdx.y;
+    const uint16_t *__restrict__ src = l.src[i];
+    int32_t *__restrict__ dst = l.dst[i];
+    const int64_t n = l.n[i], stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n; k += stride)
+        dst[k] = (int32_t)src[k];
+}
+
 __global__ __launch_bounds__(kThreads) void k_narrow(uint16_t *__restrict__ dst,
                                                      const int32_t *__restrict__ src, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
@@ -465,6 +477,18 @@ hipError_t launch_copy_labels(int32_t *dst, const Arenas &a, int64_t at, int64_t
     const unsigned want = blocks_for(n, kThreads);
     hipLaunchKernelGGL(k_widen, dim3(want > 8192u ? 8192u : want), dim3(kThreads), 0, s, dst,
                        a.lab16 + at, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen_list(const ReadbackList &l, hipStream_t s) {
+    if (l.count <= 0) return hipSuccess;
+    int64_t most = 0;
+    for (int i = 0; i < l.count; ++i) most = l.n[i] > most ? l.n[i] : most;
+    if (most <= 0) return hipSuccess;
+    // about 8192 workgroups in all, at least one per image, none idle on the largest
+    const unsigned per = (unsigned)(8192 / l.count), want = blocks_for(most, kThreads);
+    const unsigned gx = want < per ? want : (per > 0 ? per : 1u);
+    hipLaunchKernelGGL(k_widen_list, dim3(gx, (unsigned)l.count), dim3(kThreads), 0, s, l);
     return hipGetLastError();
 }
 

@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
             "seeds_warm_start": ([P, P, I64, P], S),
             "seeds_batch_warm_start": ([P, ctypes.POINTER(P), ctypes.POINTER(I64), P], S),
             "seeds_batch_labels": ([P, I32, P, I32, P], S),
+            "seeds_batch_labels_all": ([P, P, P], S),
             "seeds_batch_histograms": ([P, I32, P, P, I32, P], S),
             "seeds_batch_num_superpixels": ([P, I32], I32),
             "seeds_energy": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
@@ -253,6 +254,19 @@ def seeds_batch_labels(ctx, image: int, out: torch.Tensor, stream=None) -> torch
     _check(lib().seeds_batch_labels(ctx, image, out.data_ptr(), 0 if out.is_cuda else 1,
                                     _stream(stream)))
     return out
+
+
+def seeds_batch_labels_all(ctx, outs, stream=None) -> list:
+    """Labels of every image into the device tensors `outs` (one per image,
+    contiguous int32 of that image's H x W), written in stream order."""
+    for o in outs:
+        if o.dtype != torch.int32 or not o.is_contiguous() or not o.is_cuda:
+            raise ValueError("outs must be contiguous int32 device tensors")
+    ptrs = (ctypes.c_void_p * max(1, len(outs)))(*[o.data_ptr() for o in outs])
+    if len(outs) != seeds_batch_count(ctx):
+        raise ValueError(f"{len(outs)} outputs for {seeds_batch_count(ctx)} images")
+    _check(lib().seeds_batch_labels_all(ctx, ptrs, _stream(stream)))
+    return outs
 
 
 def seeds_batch_num_superpixels(ctx, image: int) -> int:

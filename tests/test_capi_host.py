@@ -238,6 +238,13 @@ def test_launch_floor_argument_checks(S):
     assert b"outside" in S.lib().seeds_last_error()
 
 
+def test_batch_labels_all_argument_checks(S):
+    L = S.lib()
+    outs = (ctypes.c_void_p * 1)()
+    assert L.seeds_batch_labels_all(None, outs, None) == S.SEEDS_E_INVAL
+    assert b"ctx is NULL" in S.lib().seeds_last_error()
+
+
 def test_traffic_probe_argument_checks(S):
     L = S.lib()
     us = (ctypes.c_double * 3)()

@@ -251,3 +251,53 @@ def test_mixed_batch_of_64_equals_solo_runs_and_oracle_samples(S):
     for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
         _say(f"oracle sample image {i} {specs[i]}")
         _check_image(got[i], imgs[i], Ks[i], Ls[i], 5, 4, 1, 0, what=f"image {i}")
+
+
+@pytest.mark.parametrize("P", [-1, 0, 40])
+def test_labels_of_every_image_at_once(S, P):
+    """seeds_batch_labels_all writes what seeds_batch_labels writes image by
+    image, for images at pixel level (one widening launch) and at block levels
+    (their own expansion), into outputs prefilled with a guard value."""
+    import torch
+    _say(f"batch labels of every image P={P}")
+    imgs = _images(SMALL)
+    Ks = [s[3] for s in SMALL]
+    Ls = [s[4] for s in SMALL]
+    ctx = S.seeds_batch_init(_to_dev(imgs), Ks, S.make_params(max(Ls), 5, 3, 1, 0), levels=Ls)
+    try:
+        if P < 0:
+            S.seeds_refine(ctx)
+        else:
+            S.seeds_refine_phases(ctx, P)
+        outs = [torch.full(im.shape[:2], -7, dtype=torch.int32, device="cuda") for im in imgs]
+        S.seeds_batch_labels_all(ctx, outs)
+        for i, im in enumerate(imgs):
+            one = torch.empty(im.shape[:2], dtype=torch.int32, device="cuda")
+            S.seeds_batch_labels(ctx, i, one)
+            assert torch.equal(outs[i], one), f"image {i}"
+        S.seeds_sync(ctx)
+    finally:
+        S.seeds_destroy(ctx)
+
+
+def test_labels_of_more_images_than_one_launch_takes(S):
+    """70 images: the 16-bit planes are widened 64 per launch, then 6."""
+    import torch
+    _say("batch labels of 70 images")
+    specs = [(24 + (i % 7) * 5, 30 + (i % 5) * 9, 3, 4 + i % 3, 1 + i % 2) for i in range(70)]
+    imgs = _images(specs, seed0=700)
+    ctx = S.seeds_batch_init(_to_dev(imgs), [s[3] for s in specs],
+                             S.make_params(2, 4, 2, 1, 0), levels=[s[4] for s in specs])
+    try:
+        S.seeds_refine(ctx)
+        outs = [torch.full(im.shape[:2], -7, dtype=torch.int32, device="cuda") for im in imgs]
+        S.seeds_batch_labels_all(ctx, outs)
+        for i, im in enumerate(imgs):
+            one = torch.empty(im.shape[:2], dtype=torch.int32, device="cuda")
+            S.seeds_batch_labels(ctx, i, one)
+            assert torch.equal(outs[i], one), f"image {i}"
+            ref_lab, _, _ = oracle.seeds(im, specs[i][3], specs[i][4], 4, 2, 1, 0)
+            assert np.array_equal(one.cpu().numpy(), ref_lab), f"image {i}"
+        S.seeds_sync(ctx)
+    finally:
+        S.seeds_destroy(ctx)
